@@ -1,0 +1,296 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+None of these tests calls the GPU library.  Each pin is chosen so that a
+plausible mistake in the oracle (a dropped factor, a wrong sign or index, a
+transposed operand, a wrong streaming direction) fails at least one of them.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import brute
+from oracle import closed_forms as cf
+from paper_2108_08783_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+TAU_MAGIC = 0.5 + math.sqrt(3.0 / 16.0)   # BGK bounce-back wall exactly halfway
+
+
+# ------------------------------------------------------ lattice (Sec 2.1) --
+def test_velocity_set_is_d3q19():
+    c, w = oracle.velocity_set()
+    assert c.shape == (19, 3)
+    assert len({tuple(v) for v in c}) == 19
+    norms = (c * c).sum(1)
+    assert norms[0] == 0 and set(norms[1:7]) == {1} and set(norms[7:]) == {2}
+    # every direction has its opposite in the set
+    for v in c:
+        assert any((u == -v).all() for u in c)
+    assert w[0] == pytest.approx(1 / 3, abs=1e-16)
+    assert np.allclose(w[1:7], 1 / 18, atol=1e-17) and np.allclose(w[7:], 1 / 36, atol=1e-17)
+    assert w.sum() == pytest.approx(1.0, abs=1e-15)
+
+
+def test_lattice_isotropy():
+    c, w = oracle.velocity_set()
+    c = c.astype(float)
+    d = np.eye(3)
+    m2 = np.einsum("i,ia,ib->ab", w, c, c)
+    assert np.allclose(m2, d / 3, atol=1e-15)
+    m4 = np.einsum("i,ia,ib,ic,id->abcd", w, c, c, c, c)
+    iso = (np.einsum("ab,cd->abcd", d, d) + np.einsum("ac,bd->abcd", d, d)
+           + np.einsum("ad,bc->abcd", d, d)) / 9
+    assert np.allclose(m4, iso, atol=1e-15)
+    assert np.allclose(np.einsum("i,ia->a", w, c), 0, atol=1e-16)
+    assert np.allclose(np.einsum("i,ia,ib,ic->abc", w, c, c, c), 0, atol=1e-16)
+
+
+@pytest.mark.parametrize("rho,u", [(1.0, (0, 0, 0)), (1.013, (0.03, -0.02, 0.05)),
+                                   (0.97, (-0.1, 0.07, 0.0))])
+def test_equilibrium_moments(rho, u):
+    """P1: sum feq = rho, sum feq c = rho u, sum feq c c = rho/3 I + rho u u."""
+    c, _ = oracle.velocity_set()
+    c = c.astype(float)
+    u = np.asarray(u, float)
+    f = oracle.feq(rho, u)
+    assert f.sum() == pytest.approx(rho, rel=1e-15)
+    assert np.allclose(f @ c, rho * u, atol=1e-15)
+    assert np.allclose(np.einsum("i,ia,ib->ab", f, c, c),
+                       rho / 3 * np.eye(3) + rho * np.outer(u, u), atol=1e-15)
+
+
+def test_printed_equilibrium_would_double_the_momentum_flux():
+    """The equilibrium as printed in Sec. 2.1 (no 1/2 on the quadratic terms)
+    gives a second moment rho/3 I + 2 rho u u: the reason the oracle uses the
+    standard coefficients (reading R1)."""
+    c, w = oracle.velocity_set()
+    c = c.astype(float)
+    rho, u = 1.0, np.array([0.04, -0.03, 0.02])
+    cu = c @ u
+    printed = w * rho * (1 + 3 * cu + 9 * cu ** 2 - 3 * u @ u)
+    m2 = np.einsum("i,ia,ib->ab", printed, c, c)
+    assert np.allclose(m2, rho / 3 * np.eye(3) + 2 * rho * np.outer(u, u), atol=1e-15)
+    assert not np.allclose(oracle.feq(rho, u), printed)
+
+
+# ------------------------------------------- unit conversions (Table A1) --
+def test_table_a1_relaxation_times_and_womersley_number():
+    g = json.load(open(os.path.join(GOLDEN, "table_a1.json")))
+    nu = g["fluid"]["mu"] / g["fluid"]["rho"]
+    # the cylinders use the Sec. 2.4 fluid; the artery rows do not state theirs
+    for case in [c for c in g["cases"] if c["name"].startswith("Cylinder")]:
+        tau = cf.tau_from_physical(nu, case["dx"], case["dt"])
+        assert round(tau, 3) == pytest.approx(case["tau"], abs=1.5e-3), case["name"]
+    cyl = g["cylinder"]
+    alpha = cf.womersley_number(cyl["R_m"], 2 * math.pi / cyl["period_s"], g["fluid"]["rho"],
+                                g["fluid"]["mu"])
+    assert alpha == pytest.approx(cyl["alpha_printed"], rel=1e-12)
+    # the 4 cm cylinder at R = 50 dx: lattice stiffness of the Sec. 2.4 wall
+    k = cf.wall_stiffness(cyl["Y_Pa"], cyl["h_over_R"] * cyl["R_m"], cyl["sigma"], cyl["R_m"])
+    c0 = g["cases"][0]
+    k_lu = cf.stiffness_lattice(k, g["fluid"]["rho"], c0["dx"], c0["dt"])
+    assert k_lu == pytest.approx(1.79e-3, rel=5e-3)
+    # site count of the R = 50 cylinder is pi R^2 L to within the staircase
+    L = 0.04 / c0["dx"]
+    assert c0["sites"] == pytest.approx(math.pi * 50 ** 2 * L, rel=0.01)
+
+
+# ----------------------------------------------------- invariants (P2/P3) --
+def _all_bc_cylinder():
+    g = inputs.cylinder(6, 12)
+    o = oracle.Oracle(g.labels, 0.8, segment=g.segment, normal=g.normal,
+                      iolet_weight=g.iolet_weight)
+    return g, o
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_rest_state_is_invariant(mode):
+    """P2: uniform rho = 1, u = 0 with every boundary type at rest stays put."""
+    g, o = _all_bc_cylinder()
+    o.set_wall(mode, F=0.85, P0=1.0 / 3.0, k=[1e-2])
+    o.set_iolet(0, 1, 0.0, amp=0.5, period=50.0, direction=(0, 0, 1))   # velocity, zero mean
+    o.set_iolet(1, 0, 1.0)                                              # density 1
+    o.init_fields()
+    f0 = o.populations()
+    o.step(300)
+    assert np.abs(o.populations() - f0).max() <= 2e-15
+
+
+def test_closed_box_conserves_mass():
+    """P3: bounce-back walls on all sides, random populations: total mass is
+    constant up to rounding over 2000 steps."""
+    g = inputs.closed_box(10, 9, 8)
+    o = oracle.Oracle(g.labels, 0.8)
+    o.set_wall(0)
+    rng = np.random.default_rng(7)
+    _, w = oracle.velocity_set()
+    o.set_populations(w[None, :] * (1 + 0.01 * rng.uniform(-1, 1, (o.n, 19))))
+    m0 = o.populations().sum()
+    o.step(2000)
+    assert abs(o.populations().sum() - m0) / m0 <= 1e-12
+
+
+def test_elastic_wall_with_dilation_changes_mass():
+    """The GZS-type elastic wall is not mass conserving in motion (recorded
+    as a property, not a defect): a closed elastic box started with motion
+    must change its mass, while bounce-back keeps it."""
+    g = inputs.closed_box(8, 8, 8)
+    o = oracle.Oracle(g.labels, 0.8)
+    o.set_wall(1, F=0.5, P0=0.0, k=[1e-2])
+    u0 = np.zeros((o.n, 3))
+    u0[:, 0] = 0.02
+    o.init_fields(None, u0)
+    m0 = o.populations().sum()
+    o.step(50)
+    assert abs(o.populations().sum() - m0) / m0 > 1e-8
+
+
+# ------------------------------------------------ brute force (P6) -------
+@pytest.mark.parametrize("mode,seed", [(0, 1), (1, 2), (1, 3)])
+def test_one_step_matches_brute_force(mode, seed):
+    rng = np.random.default_rng(seed)
+    geo = inputs.random_labels((6, 7, 6), rng)
+    tau = 0.7
+    o = oracle.Oracle(geo.labels, tau, segment=geo.segment, iolet_weight=geo.iolet_weight)
+    k = [0.02, 0.005, 1e-3]
+    F, P0 = 0.6, 0.331
+    o.set_wall(mode, F=F, P0=P0, k=k)
+    iol = {0: dict(kind=0, a0=1.002, amp=0.3, period=17.0, phase=0.4,
+                   direction=geo.iolets[0]["direction"]),
+           1: dict(kind=1, a0=0.03, amp=0.5, period=11.0, phase=-1.0,
+                   direction=geo.iolets[1]["direction"])}
+    for i, p in iol.items():
+        o.set_iolet(i, p["kind"], p["a0"], p["amp"], p["period"], p["phase"], p["direction"])
+    o.init_fields()
+    o.step(5)                       # advance the drive clock
+    c, w = oracle.velocity_set()
+    f0 = w[None, :] * (1 + 0.05 * rng.uniform(-1, 1, (o.n, 19)))
+    f0[:, 1:7] += 0.004 * rng.uniform(-1, 1, (o.n, 6))
+    o.set_populations(f0)
+    t = o.time
+    o.step(1)
+    coords = o.coords()
+    ref = brute.step(geo.labels, brute.from_array(coords, f0, c), tau, mode=mode, F=F, P0=P0,
+                     k_seg=k, segment=geo.segment, iolets=iol,
+                     iolet_weight=geo.iolet_weight, t=t)
+    assert np.abs(o.populations() - brute.to_array(coords, ref, c)).max() <= 1e-14
+
+
+# ------------------------------------------------ symmetry (P9) -----------
+def test_mirror_symmetry():
+    rng = np.random.default_rng(11)
+    geo = inputs.random_labels((7, 6, 8), rng)
+    res = []
+    for g in (geo, inputs.mirror_x(geo)):
+        o = oracle.Oracle(g.labels, 0.75, segment=g.segment, iolet_weight=g.iolet_weight)
+        o.set_wall(1, F=0.4, P0=0.333, k=[0.01, 0.003, 0.02])
+        o.set_iolet(0, 0, 1.001, 0.2, 13.0)
+        o.set_iolet(1, 1, 0.02, 0.0, 1.0, 0.0, g.iolets[1]["direction"])
+        o.init_fields()
+        o.step(40)
+        rho, u, wss, dr = o.read()
+        res.append((o.coords(), rho, u, wss, dr))
+    (c0, r0, u0, w0, d0), (c1, r1, u1, w1, d1) = res
+    nx = geo.labels.shape[2]
+    key0 = {tuple(v): i for i, v in enumerate(c0)}
+    perm = np.array([key0[(nx - 1 - x, y, z)] for x, y, z in c1])
+    assert np.abs(r1 - r0[perm]).max() <= 1e-13
+    assert np.abs(u1[:, 0] + u0[perm, 0]).max() <= 1e-13
+    assert np.abs(u1[:, 1:] - u0[perm, 1:]).max() <= 1e-13
+    assert np.abs(w1 - w0[perm]).max() <= 1e-13
+    assert np.abs(d1 - d0[perm]).max() <= 1e-13
+
+
+# ------------------------------------------------ Poiseuille (P4) --------
+def _channel(H, tau, mode=0, F=0.0, steps_factor=3.0):
+    """Wide duct (width 8H: the centre plane is a plane channel to ~1e-5),
+    density-driven; returns (y, u_z, rho-mean, G, wss) on the centre line of
+    the mid-section."""
+    W, L = 8 * H, 4 * H
+    g = inputs.duct(W, H, L)
+    o = oracle.Oracle(g.labels, tau)
+    o.set_wall(mode, F=F, P0=0.0, k=[1e30])
+    o.set_iolet(0, 0, 1.0001)
+    o.set_iolet(1, 0, 0.9999)
+    o.init_fields()
+    nu = (tau - 0.5) / 3
+    o.step(int(steps_factor * 14 * H * H / (math.pi ** 2 * nu) / (1 - F)))
+    rho, u, wss, _ = o.read()
+    xyz = o.coords()
+    zc = L // 2
+
+    def mean_rho(z):
+        return rho[xyz[:, 2] == z].mean()
+
+    G = -(mean_rho(zc + 1) - mean_rho(zc - 1)) / 2 / 3
+    sel = (xyz[:, 2] == zc) & (xyz[:, 0] == W // 2)
+    y = xyz[sel, 1] - (H + 1) / 2
+    return y, u[sel, 2], rho[sel].mean(), G, wss[sel], nu
+
+
+def test_poiseuille_exact_at_halfway_tau():
+    """P4: with tau = 1/2 + sqrt(3/16) BGK bounce-back puts the wall exactly
+    halfway between nodes, so the mid-section is the plane Poiseuille
+    parabola of half-width H/2."""
+    H = 8
+    y, uz, rho, G, wss, nu = _channel(H, TAU_MAGIC)
+    ua = cf.plane_poiseuille(y, H / 2, G, rho * nu)
+    assert np.abs(uz - ua).max() / ua.max() <= 1e-3
+    # wall shear stress at the wall-adjacent node equals G times its distance
+    # from the centre plane (steady momentum balance)
+    edge = np.abs(y) == y.max()
+    assert wss[edge] == pytest.approx(G * y.max(), rel=2e-3)
+    assert np.all(wss[~edge] == 0.0)
+
+
+def test_poiseuille_second_order_convergence():
+    """P4: at tau = 0.8 the bounce-back wall location error makes the error
+    fall about 4x per doubling of the channel width."""
+    errs = []
+    for H in (4, 8):
+        y, uz, rho, G, _, nu = _channel(H, 0.8)
+        ua = cf.plane_poiseuille(y, H / 2, G, rho * nu)
+        errs.append(np.abs(uz - ua).max() / ua.max())
+    assert errs[1] < 0.05
+    assert errs[0] / errs[1] > 3.0
+
+
+@pytest.mark.parametrize("F", [0.0, 0.5])
+def test_elastic_wall_slip_poiseuille(F):
+    """P5: with infinite stiffness the elastic rule sets the wall-node velocity
+    to F times the fluid-node velocity (Sec. 2.3 with Delta E = 0); the steady
+    profile is the parabola through that slip condition.  The GZS
+    extrapolation is not exact for a parabola, so the error must shrink
+    roughly 3-4x per doubling and be a few percent at half-width 4."""
+    errs = []
+    for H in (4, 8):
+        y, uz, rho, G, _, nu = _channel(H, 0.8, mode=1, F=F)
+        b2 = cf.slip_half_width_sq((H + 1) / 2, F)
+        ua = G / (2 * rho * nu) * (b2 - y ** 2)
+        errs.append(np.abs(uz - ua).max() / ua.max())
+    assert errs[1] < 0.05
+    assert errs[0] / errs[1] > 2.5
+
+
+def test_elastic_extension_clamp_and_monotonicity():
+    """Sec. 2.4 extension law with reading R4: below P0 the wall is rigid at
+    the wall node (identical to infinite stiffness); above P0 a softer wall
+    gives a larger wall-node slip, hence more flow."""
+    g = inputs.duct(16, 6, 24)
+    res = {}
+    for name, P0, k in [("inf", 0.0, 1e30), ("clamped", 1.0, 1e-3), ("soft", 0.0, 1e-2)]:
+        o = oracle.Oracle(g.labels, 0.8)
+        o.set_wall(1, F=0.3, P0=P0, k=[k])
+        o.set_iolet(0, 0, 1.0005)
+        o.set_iolet(1, 0, 0.9995)
+        o.init_fields()
+        o.step(300)
+        res[name] = o.read()
+    assert np.array_equal(res["inf"][1], res["clamped"][1])
+    assert res["soft"][1][:, 2].sum() > res["inf"][1][:, 2].sum() * 1.01
+    dr = res["soft"][3]
+    assert dr.max() > 1.0 and np.all((dr == 0) | (dr >= 1.0))
