@@ -1,0 +1,266 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) elastic-wall D3Q19 lattice Boltzmann
+ * library.
+ *
+ * The method is that of McCullough & Coveney, "An efficient, localised
+ * approach for the simulation of elastic blood vessels using the lattice
+ * Boltzmann method" (2021):
+ *   - D3Q19 lattice, single-relaxation-time (BGK) collision and streaming
+ *     over the fluid sites of a sparse vessel geometry (Sec. 2.1, eqs.
+ *     LBE_SRT, feq, Density, Momentum, Pressure);
+ *   - the localised elastic wall: a GZS-type link rule with Delta = 1 whose
+ *     wall-node velocity U_w = U_R + ((Delta r - Delta x)/Delta r)(U_f - U_R),
+ *     U_R = F U_f, with Delta r = Delta x + Delta E and the extension
+ *     Delta E following the local pressure (Sec. 2.3 and the extension law of
+ *     Sec. 2.4);
+ *   - bounce-back rigid walls (Sec. 2.4), velocity inlets with a profile
+ *     weight map and fixed-pressure (density) outlets (Sec. 3).
+ *
+ * Conventions
+ *   - Every function returns an int status: LBM_OK (0) or a negative
+ *     LBM_E* code.  No C++ exception crosses this boundary.  The message of
+ *     the last failure is returned by lbm_last_error(ctx) (ctx may be NULL
+ *     for failures of lbm_create_geometry / lbm_plan_*).
+ *   - Lattice units throughout: Delta x = Delta t = 1, C_s^2 = 1/3,
+ *     pressure p = rho / 3.
+ *   - Voxel arrays are nx*ny*nz, x fastest, then y, then z.
+ *   - Sites are the fluid voxels.  The canonical site order is the raster
+ *     order of each instance's fluid voxels, instances concatenated; every
+ *     per-site array exchanged through this API is in that order and covers
+ *     one instance.
+ *   - Population order (checkpoint calls): 0 rest; 1..6 = +x,-x,+y,-y,+z,-z;
+ *     7..18 = face diagonals (x,y), (x,z), (y,z) families, each ordered
+ *     (+,+), (-,-), (+,-), (-,+).
+ *   - Host arrays passed in are read during the call and never retained;
+ *     host arrays passed out are written before the call returns.  All
+ *     device memory is owned by the context and freed by lbm_destroy.
+ *   - A context is thread-compatible, not thread-safe: one host thread at a
+ *     time.  Work is enqueued on the context's own HIP stream
+ *     (lbm_get_stream); lbm_step is asynchronous, the read calls
+ *     synchronise.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define LBM_OK 0
+#define LBM_EINVAL (-1)    /* invalid argument or geometry                  */
+#define LBM_ENOMEM (-2)    /* host or device allocation failed              */
+#define LBM_EDEVICE (-3)   /* HIP runtime / launch failure                  */
+#define LBM_EDIVERGED (-4) /* a non-finite value was read back              */
+#define LBM_ESTATE (-5)    /* call not valid in the current state           */
+
+/* ---- enums -------------------------------------------------------------- */
+/* Storage type of the populations.  F64 and F32 store f_i - w_i in the
+ * named type and collide in that type; F16DEV and BF16DEV store the
+ * deviation f_i - w_i in 16 bits (round to nearest even) and collide in
+ * FP32.  Wall distance and pressure are always evaluated in FP32 or
+ * better. */
+enum lbm_dtype { LBM_F64 = 0, LBM_F32 = 1, LBM_F16DEV = 2, LBM_BF16DEV = 3 };
+
+/* Wall rule of an instance (Sec. 2.3 elastic; Sec. 2.4 bounce-back). */
+enum lbm_wall_mode { LBM_WALL_BOUNCEBACK = 0, LBM_WALL_ELASTIC = 1 };
+
+/* Inlet/outlet kind (Sec. 3): a DENSITY iolet prescribes rho and keeps the
+ * fluid node's velocity, a VELOCITY iolet prescribes u = weight * value * dir
+ * and keeps the fluid node's density.  Both write the link's post-collision
+ * value as feq(prescribed) + (1 - 1/tau) fneq(fluid node). */
+enum lbm_iolet_kind { LBM_IOLET_DENSITY = 0, LBM_IOLET_VELOCITY = 1 };
+
+/* Voxel labels. */
+#define LBM_LABEL_WALL 0
+#define LBM_LABEL_FLUID 1
+#define LBM_LABEL_IOLET0 2 /* label 2 + id, id = 0..253 */
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* One vessel instance.  labels: 0 wall/solid, 1 fluid, 2+id iolet.  A fluid
+ * voxel must not lie on the array border.  The type of each link of a fluid
+ * site is decided by the label of its upstream voxel x - c_i.
+ *   segment      optional (NULL: all 0): wall segment id per voxel, selects
+ *                the stiffness k of lbm_set_wall_params at fluid voxels;
+ *   normal       optional (NULL: normalised sum of -c_i over the site's wall
+ *                links): outward unit normal, 3 floats per voxel, used for
+ *                the wall shear stress;
+ *   iolet_weight optional (NULL: 1): profile weight per voxel, multiplies a
+ *                velocity iolet's value at the fluid site next to it. */
+typedef struct {
+    int32_t nx, ny, nz;
+    const uint8_t* labels;
+    const uint16_t* segment;
+    const float* normal;
+    const float* iolet_weight;
+} lbm_instance_desc;
+
+typedef struct {
+    int64_t n_sites;         /* fluid sites, all instances                   */
+    int64_t n_boundary;      /* sites handled by the boundary pass           */
+    int64_t n_wall_sites;    /* sites with at least one wall link            */
+    int64_t n_wall_links;    /* links whose upstream voxel is a wall         */
+    int64_t n_iolet_links;   /* links whose upstream voxel is an iolet       */
+    int64_t step;            /* steps enqueued since creation                */
+    int32_t n_instances;
+    int32_t dtype;           /* enum lbm_dtype                               */
+    int32_t index_bits;      /* 16 or 32: width of the neighbour table       */
+    int32_t block_size;      /* threads per block of the update kernel       */
+    int32_t use_graph;       /* 1: lbm_step replays captured HIP graphs      */
+    int32_t xcd_remap;       /* 1: block -> XCD-contiguous site ranges       */
+    int32_t nontemporal;     /* 1: population stores bypass the caches       */
+    int32_t reserved;
+    double bytes_per_site_algorithmic; /* 2 * 19 * sizeof(stored type)       */
+    double bytes_per_site_model;       /* + neighbour table + boundary data  */
+    int64_t device_bytes;    /* device memory held by the context            */
+} lbm_info;
+
+/* ---- lifetime ----------------------------------------------------------- */
+
+/* Builds the site list, the neighbour (pull) table and the compacted
+ * boundary list of n_inst instances (Sec. 2.1 streaming over the fluid
+ * nodes; Sec. 2.3 link classification), allocates device memory on the
+ * current HIP device and initialises every instance to rho = 1, u = 0 with
+ * bounce-back walls.  tau is the BGK relaxation time (Sec. 2.1), tau > 1/2.
+ * Errors: LBM_EINVAL (n_inst <= 0, tau <= 1/2, unknown dtype, no fluid
+ * voxel, fluid on the border, a site touching two different iolets, more
+ * than 2^31/19 sites), LBM_ENOMEM, LBM_EDEVICE. */
+int lbm_create_geometry(lbm_ctx** out, const lbm_instance_desc* inst, int n_inst, int dtype,
+                        double tau);
+
+/* Frees every resource of the context; NULL is accepted. */
+int lbm_destroy(lbm_ctx* ctx);
+
+/* Message of the last failure on ctx (or of the last context-less failure
+ * of this thread when ctx is NULL).  Never NULL; owned by the library. */
+const char* lbm_last_error(const lbm_ctx* ctx);
+
+/* ---- parameters --------------------------------------------------------- */
+
+/* Wall rule of instance inst (Sec. 2.3, Sec. 2.4).  mode: enum
+ * lbm_wall_mode.  F = U_R/U_f in [0, 1).  P0: pressure at which the
+ * extension vanishes (lattice units).  k_per_segment[s] > 0: stiffness of
+ * segment s, Delta E = max(0, (p - P0)/k) (k = Y h / ((1 - sigma^2) R^2) in
+ * lattice units).  n_seg must cover every segment id present at the
+ * instance's fluid voxels.  Takes effect for the next step.  Errors:
+ * LBM_EINVAL. */
+int lbm_set_wall_params(lbm_ctx* ctx, int inst, int mode, double F, double P0,
+                        const double* k_per_segment, int n_seg);
+
+/* Drive of iolet id of instance inst (Sec. 3).  value(t) = a0 (1 + amp
+ * sin(2 pi t / period + phase)), t = steps since the instance's last
+ * lbm_init_fields; amp = 0 gives a steady value (period is then ignored,
+ * otherwise period > 0).  DENSITY: value is rho.  VELOCITY: the prescribed
+ * velocity at fluid site x is iolet_weight(x) * value(t) * dir, dir (3
+ * doubles) the unit direction into the vessel.  Every iolet present in the
+ * labels must be set before lbm_step.  Errors: LBM_EINVAL. */
+int lbm_set_iolet(lbm_ctx* ctx, int inst, int id, int kind, double a0, double amp,
+                  double period, double phase, const double* dir);
+
+/* Sets f = feq(rho, u) at every site of instance inst (Sec. 2.1 eq. feq);
+ * rho (n_inst_sites doubles) and u (3 * n_inst_sites doubles, xyz per site)
+ * in canonical order; NULL means rho = 1 / u = 0.  Resets the instance's
+ * drive clock to t = 0.  Errors: LBM_EINVAL, LBM_EDEVICE. */
+int lbm_init_fields(lbm_ctx* ctx, int inst, const double* rho, const double* u);
+
+/* Same as lbm_init_fields with a DEVICE array rho_u of 4 floats per site
+ * (rho, ux, uy, uz) in canonical order for instance inst; the call is
+ * enqueued on the context's stream after all previous work. */
+int lbm_init_fields_device(lbm_ctx* ctx, int inst, const float* rho_u_dev);
+
+/* ---- stepping ----------------------------------------------------------- */
+
+/* Advances every instance by n >= 0 steps (Sec. 2.1 eq. LBE_SRT with the
+ * boundary rules), asynchronously on the context's stream.  Errors:
+ * LBM_ESTATE (an iolet without parameters), LBM_EDEVICE. */
+int lbm_step(lbm_ctx* ctx, int64_t n);
+
+/* Blocks until all work of the context has finished. */
+int lbm_sync(lbm_ctx* ctx);
+
+/* The context's HIP stream (hipStream_t) in *stream. */
+int lbm_get_stream(lbm_ctx* ctx, void** stream);
+
+/* Enqueues n steps between two HIP events recorded on the context's stream
+ * and returns the elapsed milliseconds (synchronises). */
+int lbm_time_steps(lbm_ctx* ctx, int64_t n, double* ms);
+
+/* ---- read-out ----------------------------------------------------------- */
+
+/* Fields of instance inst at the current time from f(t) (Sec. 2.1 eqs.
+ * Density, Momentum, Pressure; p = rho/3).  Outputs (any may be NULL), in
+ * canonical order of the instance's sites:
+ *   rho     n doubles;
+ *   u       3n doubles (xyz per site);
+ *   wss     n doubles: |t - (t.n) n|, t = sigma n,
+ *           sigma = -(1 - 1/(2 tau)) sum_i fneq_i c_i c_i, at sites with at
+ *           least one wall link, 0 elsewhere;
+ *   wall_dr n floats: Delta r = 1 + max(0, (p - P0)/k) at wall sites of an
+ *           elastic instance, 0 elsewhere (Sec. 2.3, 2.4).
+ * Synchronises.  Returns LBM_EDIVERGED if any rho or u is not finite (the
+ * outputs are still written). */
+int lbm_read_fields(lbm_ctx* ctx, int inst, double* rho, double* u, double* wss,
+                    float* wall_dr);
+
+/* Populations f_i(t) of instance inst, n * 19 doubles, site-major, in the
+ * population order above (checkpoint).  Synchronises. */
+int lbm_read_populations(lbm_ctx* ctx, int inst, double* f);
+
+/* Overwrites f_i(t) of instance inst (same layout), keeping its clock. */
+int lbm_write_populations(lbm_ctx* ctx, int inst, const double* f);
+
+/* Periodicity monitor (cycle-to-cycle change).  Compares the current
+ * velocity and pressure of instance inst with the snapshot taken by the
+ * previous call and stores a new snapshot:
+ *   delta_u = max_x |u(x) - u_prev(x)|_inf / max_x |u(x)|_inf,
+ *   delta_p = max_x |p(x) - p_prev(x)| / max_x |p(x) - P0|.
+ * The first call after creation or lbm_init_fields returns +inf for both.
+ * Synchronises. */
+int lbm_cycle_delta(lbm_ctx* ctx, int inst, double* delta_u, double* delta_p);
+
+/* ---- introspection / tuning ---------------------------------------------- */
+
+int lbm_get_info(const lbm_ctx* ctx, lbm_info* info);
+
+/* Number of sites of instance inst in *n. */
+int lbm_instance_sites(const lbm_ctx* ctx, int inst, int64_t* n);
+
+/* Launch configuration of the update kernel.  block_size in {64, 128, 256,
+ * 512, 1024}; index_bits 16 or 32 (16 only if every neighbour offset fits,
+ * else LBM_EINVAL); use_graph, xcd_remap, nontemporal booleans.  A value of
+ * -1 keeps the current setting. */
+int lbm_set_launch(lbm_ctx* ctx, int block_size, int index_bits, int use_graph, int xcd_remap,
+                   int nontemporal);
+
+/* Times every launch configuration on the context's own state for
+ * steps_per_trial steps each (the populations are saved and restored), keeps
+ * the fastest and writes its steps per second in *best_rate (may be NULL).
+ * Results are cached in-process per (sites, boundary sites, dtype). */
+int lbm_autotune(lbm_ctx* ctx, int steps_per_trial, double* best_rate);
+
+/* ---- host-only geometry plan (no device needed) -------------------------- */
+
+/* Runs the host part of lbm_create_geometry for n_inst instances (wall mode
+ * bounce-back for instances whose wall_mode[i] is 0, elastic for 1; NULL
+ * means all bounce-back) and writes
+ *   counts[6]  = {n_sites, n_boundary, n_wall_sites, n_wall_links,
+ *                 n_iolet_links, max |neighbour offset|};
+ *   nbr        = 18 * n_sites int32 if not NULL: for direction i = 1..18
+ *                (row i-1) and site x, the offset d such that the upstream
+ *                site is x + d, or INT32_MIN for a bounce-back link,
+ *                INT32_MIN + 1 for a link handled by the boundary pass;
+ *   boundary   = n_boundary int32 site indices if not NULL;
+ *   bmask      = n_boundary uint32 if not NULL: bit i set for each link i
+ *                whose upstream voxel is a wall (elastic) or an iolet.
+ * No device call is made.  Errors: LBM_EINVAL. */
+int lbm_plan_export(const lbm_instance_desc* inst, int n_inst, const int* wall_mode,
+                    int64_t* counts, int32_t* nbr, int32_t* boundary, uint32_t* bmask);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H */

@@ -1,0 +1,67 @@
+// Host-side geometry plan: fluid-site enumeration, the per-link
+// classification of Sec. 2.3 (fluid / wall / iolet upstream voxel), the pull
+// (neighbour) table and the compacted boundary list.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm.h"
+
+namespace lbm {
+
+// Host classification sentinels (before the wall mode is applied).
+constexpr int32_t H_WALL = INT32_MIN;
+constexpr int32_t H_IOLET = INT32_MIN + 1;
+
+struct InstanceGeom {
+    int nx = 0, ny = 0, nz = 0;
+    int64_t offset = 0;   // first global site
+    int64_t n = 0;        // sites
+    int n_seg = 1;        // max segment id at fluid voxels + 1
+    int n_iolet = 0;      // max iolet id adjacent to a fluid site + 1
+    std::vector<uint8_t> iolet_used;  // per id: some link reads it
+    int64_t wall_begin = 0, wall_end = 0;  // range in the wall-site list
+};
+
+struct Plan {
+    int64_t N = 0;
+    std::vector<InstanceGeom> inst;
+    // nbr[(i-1)*N + x]: offset d (upstream = x + d) or H_WALL / H_IOLET.
+    std::vector<int32_t> nbr;
+    std::vector<uint8_t> site_iolet;   // iolet id of the site's iolet links, 255 if none
+    std::vector<uint16_t> site_seg;
+    std::vector<float> site_w;         // iolet profile weight
+    std::vector<uint32_t> site_inst;
+    // sites with at least one wall link, ascending
+    std::vector<int32_t> wall_site;
+    std::vector<double> wall_normal;   // 3 per wall site (unit, normalised in FP64)
+    int64_t n_wall_links = 0, n_iolet_links = 0;
+    int64_t max_abs_offset = 0;
+};
+
+// Returns an empty string on success, else the reason.
+std::string build_plan(const lbm_instance_desc* desc, int n_inst, Plan& plan);
+
+// The boundary list for a given wall mode per instance (0 bounce-back,
+// 1 elastic): sites having at least one link handled by the boundary pass
+// (elastic wall link or iolet link).
+struct BoundaryList {
+    std::vector<int32_t> site;
+    std::vector<uint32_t> wall;   // bits 1..18 elastic wall links | inst << 19
+    std::vector<uint32_t> io;     // bits 1..18 iolet links | global iolet slot << 19
+    std::vector<int32_t> kidx;    // index into the global stiffness table
+    std::vector<float> weight;    // iolet profile weight
+};
+
+void build_boundary(const Plan& plan, const std::vector<int>& mode,
+                    const std::vector<int>& seg_off, const std::vector<int>& iolet_off,
+                    BoundaryList& out);
+
+// Device neighbour table of width I for the given wall modes.
+template <typename I>
+void build_device_nbr(const Plan& plan, const std::vector<int>& mode, int64_t n_pad,
+                      std::vector<I>& out);
+
+}  // namespace lbm

@@ -1,0 +1,567 @@
+// HIP kernels for gfx950: the fused pull-scheme collide-and-stream update
+// with its compacted boundary pass, initialisation, read-out, wall shear
+// stress, checkpoint and periodicity kernels.
+//
+// State convention.  Buffer S(t) holds, for every site y and direction i,
+// the post-collision deviation h*_i(y, t-1) = f*_i - w_i in plane i at y
+// (structure of arrays, plane stride np).  A site x pulls f_i(x, t) from
+// S(t) at y = x - c_i when that voxel is fluid, and from its own opposite
+// slot (plane opp(i), site x) when it is not: for a bounce-back wall that slot
+// holds f*_opp(i)(x) (Sec. 2.4), for an elastic wall or an iolet link the
+// boundary pass of the previous step wrote the link's value there (Sec. 2.3,
+// Sec. 3).  Every slot is read by exactly one site per step.
+#include <hip/hip_runtime.h>
+
+#include "../../include/lbm.h"
+#include "d3q19.hpp"
+#include "kernels.hpp"
+
+namespace lbm {
+namespace {
+
+// ---------------------------------------------------------------- codecs --
+// Populations are stored as deviations h = f - w (Sec. 2.1 weights).  FP16
+// deviations are scaled by 2^10 (exact) so that small values stay normal;
+// BF16 keeps FP32's exponent range and needs no scale.  Conversions to
+// 16 bits round to nearest even.
+template <int DT>
+struct Codec;
+template <>
+struct Codec<LBM_F64> {
+    using raw = double;
+    using acc = double;
+    __device__ static acc dec(raw v) { return v; }
+    __device__ static raw enc(acc v) { return v; }
+};
+template <>
+struct Codec<LBM_F32> {
+    using raw = float;
+    using acc = float;
+    __device__ static acc dec(raw v) { return v; }
+    __device__ static raw enc(acc v) { return v; }
+};
+template <>
+struct Codec<LBM_F16DEV> {
+    using raw = uint16_t;
+    using acc = float;
+    __device__ static acc dec(raw v) {
+        return (float)__builtin_bit_cast(_Float16, v) * (1.0f / 1024.0f);
+    }
+    __device__ static raw enc(acc v) { return __builtin_bit_cast(uint16_t, (_Float16)(v * 1024.0f)); }
+};
+template <>
+struct Codec<LBM_BF16DEV> {
+    using raw = uint16_t;
+    using acc = float;
+    __device__ static acc dec(raw v) { return __uint_as_float((uint32_t)v << 16); }
+    __device__ static raw enc(acc v) {
+        uint32_t b = __float_as_uint(v);
+        b += 0x7FFFu + ((b >> 16) & 1u);
+        return (raw)(b >> 16);
+    }
+};
+
+template <typename acc>
+struct W {
+    static constexpr acc w0 = (acc)(1.0 / 3.0);
+    static constexpr acc w1 = (acc)(1.0 / 18.0);
+    static constexpr acc w2 = (acc)(1.0 / 36.0);
+};
+
+__device__ __forceinline__ constexpr int dopp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+
+// ---------------------------------------------------------------- gather --
+template <typename I>
+__device__ __forceinline__ void load_offsets(const I* __restrict__ nbr, int64_t np, int x,
+                                             I (&d)[18]) {
+#pragma unroll
+    for (int i = 0; i < 18; ++i) d[i] = nbr[(int64_t)i * np + x];
+}
+
+// f_i(x, t) - w_i for all i from buffer A (both sentinels redirect to the
+// site's own opposite slot).
+template <int DT, typename I>
+__device__ __forceinline__ void gather(const typename Codec<DT>::raw* __restrict__ A, int64_t np,
+                                       int x, const I (&d)[18],
+                                       typename Codec<DT>::acc (&h)[Q]) {
+    h[0] = Codec<DT>::dec(A[x]);
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const I di = d[i - 1];
+        const bool redirect = di <= Sentinel<I>::GHOST;
+        const int64_t idx = redirect ? (int64_t)dopp(i) * np + x : (int64_t)i * np + x + di;
+        h[i] = Codec<DT>::dec(A[idx]);
+    }
+}
+
+// ------------------------------------------------------------- physics ----
+// Sec. 2.1 eqs. Density and Momentum in deviation form: sum_i w_i = 1 and
+// sum_i w_i c_i = 0, so rho = 1 + sum h_i and rho u = sum h_i c_i.
+template <typename acc>
+struct Mom {
+    acc drho, rho, ux, uy, uz;
+};
+
+template <typename acc>
+__device__ __forceinline__ Mom<acc> moments(const acc (&h)[Q]) {
+    Mom<acc> m;
+    acc s = h[0];
+#pragma unroll
+    for (int i = 1; i < Q; ++i) s += h[i];
+    const acc jx = (h[1] - h[2]) + (h[7] - h[8]) + (h[9] - h[10]) + (h[11] - h[12]) + (h[13] - h[14]);
+    const acc jy = (h[3] - h[4]) + (h[7] - h[8]) - (h[9] - h[10]) + (h[15] - h[16]) + (h[17] - h[18]);
+    const acc jz = (h[5] - h[6]) + (h[11] - h[12]) - (h[13] - h[14]) + (h[15] - h[16]) - (h[17] - h[18]);
+    m.drho = s;
+    m.rho = (acc)1 + s;
+    const acc inv = (acc)1 / m.rho;
+    m.ux = jx * inv;
+    m.uy = jy * inv;
+    m.uz = jz * inv;
+    return m;
+}
+
+// Sec. 2.1 eq. feq (standard 1/2 factors) minus w_i:
+// w_i (drho + rho (3 c.u + 9/2 (c.u)^2 - 3/2 u.u)).  Pairs (2k+1, 2k+2) are
+// opposite directions with c.u = +-cu_k.
+template <typename acc>
+__device__ __forceinline__ void heq(acc drho, acc rho, acc ux, acc uy, acc uz, acc (&e)[Q]) {
+    const acc r0 = drho - rho * (acc)1.5 * (ux * ux + uy * uy + uz * uz);
+    const acc r3 = (acc)3 * rho, r45 = (acc)4.5 * rho;
+    e[0] = W<acc>::w0 * r0;
+    const acc cu[9] = {ux, uy, uz, ux + uy, ux - uy, ux + uz, ux - uz, uy + uz, uy - uz};
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const acc w = k < 3 ? W<acc>::w1 : W<acc>::w2;
+        const acc p = r3 * cu[k];
+        const acc q = r45 * cu[k] * cu[k] + r0;
+        e[2 * k + 1] = w * (q + p);
+        e[2 * k + 2] = w * (q - p);
+    }
+}
+
+template <typename acc>
+__device__ __forceinline__ acc heq_one(int i, acc drho, acc rho, acc ux, acc uy, acc uz) {
+    const acc cu = (acc)CX[i] * ux + (acc)CY[i] * uy + (acc)CZ[i] * uz;
+    const acc w = i == 0 ? W<acc>::w0 : (i <= 6 ? W<acc>::w1 : W<acc>::w2);
+    return w * (drho + rho * ((acc)3 * cu + (acc)4.5 * cu * cu - (acc)1.5 * (ux * ux + uy * uy + uz * uz)));
+}
+
+template <typename raw>
+__device__ __forceinline__ void put(raw* p, raw v, bool nt) {
+    if (nt)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
+}
+
+template <typename acc>
+__device__ __forceinline__ acc sin_acc(acc v);
+template <>
+__device__ __forceinline__ double sin_acc<double>(double v) { return sin(v); }
+template <>
+__device__ __forceinline__ float sin_acc<float>(float v) { return sinf(v); }
+
+// Drive value of an iolet at step t (Sec. 3).  The phase is reduced in
+// double so that long runs keep full precision.
+template <typename acc>
+__device__ __forceinline__ acc drive_dev(const IoletParams& q, int64_t t, acc& minus1) {
+    acc s = 0;
+    if (q.amp != 0.0) {
+        const double ph = (double)t * q.inv_period;
+        const double fr = ph - floor(ph);
+        s = sin_acc<acc>((acc)(6.283185307179586 * fr + q.phase));
+    }
+    const acc a0 = (acc)q.a0;
+    minus1 = (acc)(q.a0 - 1.0) + a0 * (acc)q.amp * s;
+    return a0 * ((acc)1 + (acc)q.amp * s);
+}
+
+// ----------------------------------------------------------- update -------
+// Block -> site-range mapping that keeps consecutive site ranges on one XCD
+// (workgroups are dispatched round-robin over the 8 XCDs, each with its own
+// L2), so that cache lines shared by neighbouring wavefronts meet in one L2.
+__device__ __forceinline__ int remap_xcd(int b, int nblk) {
+    const int per = nblk >> 3, rem = nblk & 7;
+    const int j = b & 7, k = b >> 3;
+    return j * per + (j < rem ? j : rem) + k;
+}
+
+template <int DT, typename I>
+__device__ __forceinline__ void interior_site(const StepArgs& a, int x) {
+    using raw = typename Codec<DT>::raw;
+    using acc = typename Codec<DT>::acc;
+    const raw* __restrict__ A = (const raw*)a.A;
+    raw* __restrict__ B = (raw*)a.B;
+    I d[18];
+    load_offsets<I>((const I*)a.nbr, a.np, x, d);
+    bool ghost = false;
+#pragma unroll
+    for (int i = 0; i < 18; ++i) ghost |= (d[i] == Sentinel<I>::GHOST);
+    if (ghost) return;  // updated by the boundary pass
+    acc h[Q];
+    gather<DT, I>(A, a.np, x, d, h);
+    const Mom<acc> m = moments(h);
+    acc e[Q];
+    heq(m.drho, m.rho, m.ux, m.uy, m.uz, e);
+    const acc om = (acc)a.omega;
+    const bool nt = a.nontemporal != 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) put(B + (int64_t)i * a.np + x, Codec<DT>::enc(h[i] + om * (e[i] - h[i])), nt);
+}
+
+// Boundary site: the same pull and BGK collision, then for every link i whose
+// upstream voxel is an elastic wall or an iolet the value
+//   f_i(x, t+1) = feq_i(rho', U') + (1 - 1/tau) (f_i - feq_i(rho, u))
+//              = feq_i(rho', U') + f*_i - feq_i(rho, u)
+// is written into slot (opp(i), x), which the site pulls at the next step.
+//   elastic wall (Sec. 2.3): rho' = rho, U' = s u,
+//     s = (F + Delta r - 1) / Delta r, Delta r = 1 + Delta E,
+//     Delta E = max(0, (p - P0) / k), p = rho / 3;
+//   density iolet (Sec. 3): rho' = rho_io(t), U' = u;
+//   velocity iolet (Sec. 3): rho' = rho, U' = weight(x) u_io(t) dir.
+template <int DT, typename I>
+__device__ __forceinline__ void boundary_site(const StepArgs& a, int j) {
+    using raw = typename Codec<DT>::raw;
+    using acc = typename Codec<DT>::acc;
+    const raw* __restrict__ A = (const raw*)a.A;
+    raw* __restrict__ B = (raw*)a.B;
+    const int x = a.bsite[j];
+    I d[18];
+    load_offsets<I>((const I*)a.nbr, a.np, x, d);
+    acc h[Q];
+    gather<DT, I>(A, a.np, x, d, h);
+    const Mom<acc> m = moments(h);
+    acc e[Q];
+    heq(m.drho, m.rho, m.ux, m.uy, m.uz, e);
+    const acc om = (acc)a.omega;
+    acc hs[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) hs[i] = h[i] + om * (e[i] - h[i]);
+
+    const uint32_t bw = a.bwall[j], bi = a.bio[j];
+    const uint32_t wmask = bw & 0x7FFFEu, imask = bi & 0x7FFFEu;
+    const uint32_t inst = bw >> 19;
+    // elastic wall: slip factor s
+    acc s = 0;
+    if (wmask) {
+        const InstParams& P = a.ip[inst];
+        acc dE = (m.drho * (acc)(1.0 / 3.0) + (acc)P.dp0) * (acc)a.kinv[a.bk[j]];
+        dE = dE > (acc)0 ? dE : (acc)0;
+        s = ((acc)P.F + dE) / ((acc)1 + dE);
+    }
+    const acc wx = s * m.ux, wy = s * m.uy, wz = s * m.uz;
+    // iolet: prescribed density or velocity
+    acc idr = m.drho, ir = m.rho, ix = m.ux, iy = m.uy, iz = m.uz;
+    if (imask) {
+        const IoletParams& q = a.iop[bi >> 19];
+        const int64_t t = a.clock[a.clock_in] - a.ip[inst].t0;
+        acc vm1;
+        const acc v = drive_dev<acc>(q, t, vm1);
+        if (q.kind == LBM_IOLET_DENSITY) {
+            idr = vm1;
+            ir = v;
+        } else {
+            const acc sp = (acc)a.bw[j] * v;
+            ix = sp * (acc)q.dir[0];
+            iy = sp * (acc)q.dir[1];
+            iz = sp * (acc)q.dir[2];
+        }
+    }
+    acc out[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) out[i] = hs[i];
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const bool isw = (wmask >> i) & 1u, isi = (imask >> i) & 1u;
+        if (isw | isi) {
+            const acc pdr = isi ? idr : m.drho, pr = isi ? ir : m.rho;
+            const acc px = isi ? ix : wx, py = isi ? iy : wy, pz = isi ? iz : wz;
+            out[dopp(i)] = heq_one<acc>(i, pdr, pr, px, py, pz) + hs[i] - e[i];
+        }
+    }
+    const bool nt = a.nontemporal != 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) put(B + (int64_t)i * a.np + x, Codec<DT>::enc(out[i]), nt);
+}
+
+template <int DT, typename I>
+__global__ __launch_bounds__(1024) void k_step(StepArgs a) {
+    const int b = blockIdx.x;
+    if (b < a.n_int_blocks) {
+        const int lb = a.xcd_remap ? remap_xcd(b, a.n_int_blocks) : b;
+        const int x = lb * (int)blockDim.x + (int)threadIdx.x;
+        if (x < a.n) interior_site<DT, I>(a, x);
+    } else {
+        const int j = (b - a.n_int_blocks) * (int)blockDim.x + (int)threadIdx.x;
+        if (j < a.nb) boundary_site<DT, I>(a, j);
+    }
+    if (b == 0 && threadIdx.x == 0) a.clock[a.clock_in ^ 1] = a.clock[a.clock_in] + 1;
+}
+
+// ------------------------------------------------------------ read-out ---
+template <int DT, typename I>
+__global__ __launch_bounds__(256) void k_fields(FieldArgs a) {
+    using acc = typename Codec<DT>::acc;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.n) return;
+    const int x = a.first + k;
+    I d[18];
+    load_offsets<I>((const I*)a.nbr, a.np, x, d);
+    acc h[Q];
+    gather<DT, I>((const typename Codec<DT>::raw*)a.A, a.np, x, d, h);
+    const Mom<acc> m = moments(h);
+    if (a.rho) a.rho[k] = 1.0 + (double)m.drho;
+    if (a.u) {
+        a.u[3 * k] = (double)m.ux;
+        a.u[3 * k + 1] = (double)m.uy;
+        a.u[3 * k + 2] = (double)m.uz;
+    }
+}
+
+// Wall shear stress (sigma = -(1 - 1/(2 tau)) sum fneq c c, traction
+// t = sigma n, WSS = |t - (t.n) n|) and Delta r at the instance's wall sites.
+template <int DT, typename I>
+__global__ __launch_bounds__(256) void k_wall(WallArgs a) {
+    using acc = typename Codec<DT>::acc;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.nw) return;
+    const int x = a.wsite[k];
+    I d[18];
+    load_offsets<I>((const I*)a.nbr, a.np, x, d);
+    acc h[Q];
+    gather<DT, I>((const typename Codec<DT>::raw*)a.A, a.np, x, d, h);
+    const Mom<acc> m = moments(h);
+    acc e[Q];
+    heq(m.drho, m.rho, m.ux, m.uy, m.uz, e);
+    double S[6] = {0, 0, 0, 0, 0, 0};  // xx yy zz xy xz yz
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const double fn = (double)(h[i] - e[i]);
+        S[0] += fn * CX[i] * CX[i];
+        S[1] += fn * CY[i] * CY[i];
+        S[2] += fn * CZ[i] * CZ[i];
+        S[3] += fn * CX[i] * CY[i];
+        S[4] += fn * CX[i] * CZ[i];
+        S[5] += fn * CY[i] * CZ[i];
+    }
+    const double nx = a.wnormal[3 * k], ny = a.wnormal[3 * k + 1], nz = a.wnormal[3 * k + 2];
+    const double c = -a.stress_fac;
+    const double tx = c * (S[0] * nx + S[3] * ny + S[4] * nz);
+    const double ty = c * (S[3] * nx + S[1] * ny + S[5] * nz);
+    const double tz = c * (S[4] * nx + S[5] * ny + S[2] * nz);
+    const double tn = tx * nx + ty * ny + tz * nz;
+    const double sx = tx - tn * nx, sy = ty - tn * ny, sz = tz - tn * nz;
+    const int o = x - a.first;
+    if (a.wss) a.wss[o] = sqrt(sx * sx + sy * sy + sz * sz);
+    if (a.dr) {
+        float v = 0.0f;
+        if (a.elastic) {
+            double dE = ((double)m.drho / 3.0 + a.dp0) * a.kinv[a.wk[k]];
+            v = (float)(1.0 + (dE > 0 ? dE : 0.0));
+        }
+        a.dr[o] = v;
+    }
+}
+
+// f = feq(rho0, u0) (or given populations) scattered into the slots the
+// next pull reads.
+template <int DT, typename I>
+__global__ __launch_bounds__(256) void k_init(InitArgs a) {
+    using raw = typename Codec<DT>::raw;
+    using acc = typename Codec<DT>::acc;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.n) return;
+    const int x = a.first + k;
+    I d[18];
+    load_offsets<I>((const I*)a.nbr, a.np, x, d);
+    acc e[Q];
+    if (a.f) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) e[i] = (acc)(a.f[(int64_t)Q * k + i] - weight(i));
+    } else {
+        double r = 1.0, ux = 0, uy = 0, uz = 0;
+        if (a.rho_u) {
+            r = a.rho_u[4 * k];
+            ux = a.rho_u[4 * k + 1];
+            uy = a.rho_u[4 * k + 2];
+            uz = a.rho_u[4 * k + 3];
+        } else {
+            if (a.rho) r = a.rho[k];
+            if (a.u) {
+                ux = a.u[3 * k];
+                uy = a.u[3 * k + 1];
+                uz = a.u[3 * k + 2];
+            }
+        }
+        heq<acc>((acc)(r - 1.0), (acc)r, (acc)ux, (acc)uy, (acc)uz, e);
+    }
+    raw* A = (raw*)a.A;
+    A[x] = Codec<DT>::enc(e[0]);
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const I di = d[i - 1];
+        const bool redirect = di <= Sentinel<I>::GHOST;
+        const int64_t idx = redirect ? (int64_t)dopp(i) * a.np + x : (int64_t)i * a.np + x + di;
+        A[idx] = Codec<DT>::enc(e[i]);
+    }
+}
+
+template <int DT, typename I>
+__global__ __launch_bounds__(256) void k_read_pop(PopArgs a) {
+    using acc = typename Codec<DT>::acc;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.n) return;
+    const int x = a.first + k;
+    I d[18];
+    load_offsets<I>((const I*)a.nbr, a.np, x, d);
+    acc h[Q];
+    gather<DT, I>((const typename Codec<DT>::raw*)a.A, a.np, x, d, h);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) a.f[(int64_t)Q * k + i] = weight(i) + (double)h[i];
+}
+
+// Cycle-to-cycle change of u and p against the stored snapshot; block
+// maxima are combined with unsigned atomics on the (non-negative) float bits.
+template <int DT, typename I>
+__global__ __launch_bounds__(256) void k_delta(DeltaArgs a) {
+    using acc = typename Codec<DT>::acc;
+    __shared__ float red[4][256];
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    float v[4] = {0.f, 0.f, 0.f, 0.f};
+    if (k < a.n) {
+        const int x = a.first + k;
+        I d[18];
+        load_offsets<I>((const I*)a.nbr, a.np, x, d);
+        acc h[Q];
+        gather<DT, I>((const typename Codec<DT>::raw*)a.A, a.np, x, d, h);
+        const Mom<acc> m = moments(h);
+        const float ux = (float)m.ux, uy = (float)m.uy, uz = (float)m.uz;
+        const float dp = (float)(m.drho * (acc)(1.0 / 3.0));  // p - 1/3
+        float* sn = a.snap + 4 * (int64_t)k;
+        if (a.has_snap) {
+            v[0] = fmaxf(fabsf(ux - sn[0]), fmaxf(fabsf(uy - sn[1]), fabsf(uz - sn[2])));
+            v[2] = fabsf(dp - sn[3]);
+        }
+        v[1] = fmaxf(fabsf(ux), fmaxf(fabsf(uy), fabsf(uz)));
+        v[3] = fabsf((float)((double)dp + a.dp0));
+        sn[0] = ux;
+        sn[1] = uy;
+        sn[2] = uz;
+        sn[3] = dp;
+    }
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) red[c][t] = v[c];
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if (t < w) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) red[c][t] = fmaxf(red[c][t], red[c][t + w]);
+        }
+        __syncthreads();
+    }
+    if (t < 4) atomicMax(a.maxes + t, __float_as_uint(red[t][0]));
+}
+
+__global__ void k_zero_u32(unsigned int* p, int n) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) p[k] = 0u;
+}
+
+inline int cdiv(int64_t a, int b) { return (int)((a + b - 1) / b); }
+
+template <template <int, typename> class F, typename... Args>
+hipError_t dispatch(int dtype, int ibits, Args&&... args) {
+    if (ibits == 16) {
+        switch (dtype) {
+            case LBM_F64: return F<LBM_F64, int16_t>::run(args...);
+            case LBM_F32: return F<LBM_F32, int16_t>::run(args...);
+            case LBM_F16DEV: return F<LBM_F16DEV, int16_t>::run(args...);
+            case LBM_BF16DEV: return F<LBM_BF16DEV, int16_t>::run(args...);
+        }
+    } else {
+        switch (dtype) {
+            case LBM_F64: return F<LBM_F64, int32_t>::run(args...);
+            case LBM_F32: return F<LBM_F32, int32_t>::run(args...);
+            case LBM_F16DEV: return F<LBM_F16DEV, int32_t>::run(args...);
+            case LBM_BF16DEV: return F<LBM_BF16DEV, int32_t>::run(args...);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int DT, typename I>
+struct StepL {
+    static hipError_t run(const StepArgs& a, int block, hipStream_t s) {
+        const int nblk = a.n_int_blocks + cdiv(a.nb, block);
+        hipLaunchKernelGGL((k_step<DT, I>), dim3(nblk), dim3(block), 0, s, a);
+        return hipGetLastError();
+    }
+};
+template <int DT, typename I>
+struct FieldsL {
+    static hipError_t run(const FieldArgs& a, hipStream_t s) {
+        if (a.n == 0) return hipSuccess;
+        hipLaunchKernelGGL((k_fields<DT, I>), dim3(cdiv(a.n, 256)), dim3(256), 0, s, a);
+        return hipGetLastError();
+    }
+};
+template <int DT, typename I>
+struct WallL {
+    static hipError_t run(const WallArgs& a, hipStream_t s) {
+        if (a.nw == 0) return hipSuccess;
+        hipLaunchKernelGGL((k_wall<DT, I>), dim3(cdiv(a.nw, 256)), dim3(256), 0, s, a);
+        return hipGetLastError();
+    }
+};
+template <int DT, typename I>
+struct InitL {
+    static hipError_t run(const InitArgs& a, hipStream_t s) {
+        if (a.n == 0) return hipSuccess;
+        hipLaunchKernelGGL((k_init<DT, I>), dim3(cdiv(a.n, 256)), dim3(256), 0, s, a);
+        return hipGetLastError();
+    }
+};
+template <int DT, typename I>
+struct PopL {
+    static hipError_t run(const PopArgs& a, hipStream_t s) {
+        if (a.n == 0) return hipSuccess;
+        hipLaunchKernelGGL((k_read_pop<DT, I>), dim3(cdiv(a.n, 256)), dim3(256), 0, s, a);
+        return hipGetLastError();
+    }
+};
+template <int DT, typename I>
+struct DeltaL {
+    static hipError_t run(const DeltaArgs& a, hipStream_t s) {
+        if (a.n == 0) return hipSuccess;
+        hipLaunchKernelGGL((k_delta<DT, I>), dim3(cdiv(a.n, 256)), dim3(256), 0, s, a);
+        return hipGetLastError();
+    }
+};
+
+}  // namespace
+
+hipError_t launch_step(int dtype, int ibits, const StepArgs& a, int block, hipStream_t s) {
+    return dispatch<StepL>(dtype, ibits, a, block, s);
+}
+hipError_t launch_fields(int dtype, int ibits, const FieldArgs& a, hipStream_t s) {
+    return dispatch<FieldsL>(dtype, ibits, a, s);
+}
+hipError_t launch_wall(int dtype, int ibits, const WallArgs& a, hipStream_t s) {
+    return dispatch<WallL>(dtype, ibits, a, s);
+}
+hipError_t launch_init(int dtype, int ibits, const InitArgs& a, hipStream_t s) {
+    return dispatch<InitL>(dtype, ibits, a, s);
+}
+hipError_t launch_read_pop(int dtype, int ibits, const PopArgs& a, hipStream_t s) {
+    return dispatch<PopL>(dtype, ibits, a, s);
+}
+hipError_t launch_delta(int dtype, int ibits, const DeltaArgs& a, hipStream_t s) {
+    return dispatch<DeltaL>(dtype, ibits, a, s);
+}
+hipError_t launch_zero_u32(unsigned int* p, int n, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_u32, dim3(cdiv(n, 256)), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+}  // namespace lbm

@@ -1,0 +1,119 @@
+// Kernel interface shared by the runtime (lbm_api.cpp) and the HIP kernels
+// (kernels.hip).  Plain structs only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace lbm {
+
+// Per-instance wall parameters (Sec. 2.3, 2.4).
+struct InstParams {
+    double F;       // U_R / U_f
+    double dp0;     // 1/3 - P0: Delta E = max(0, (drho/3 + dp0) / k)
+    int64_t t0;     // step count at the instance's last initialisation
+    int32_t elastic;
+    int32_t pad;
+};
+
+// Per-iolet drive (Sec. 3): value(t) = a0 (1 + amp sin(2 pi t/period + phase)).
+struct IoletParams {
+    double a0, amp, inv_period, phase;
+    double dir[3];
+    int32_t kind;   // 0 density, 1 velocity
+    int32_t pad;
+};
+
+struct StepArgs {
+    const void* A;          // populations read (deviation f - w, SoA, plane stride np)
+    void* B;                // populations written
+    const void* nbr;        // 18 planes of neighbour offsets (width I)
+    int64_t np;             // plane stride in elements
+    int32_t n;              // fluid sites
+    int32_t n_int_blocks;   // blocks of the interior part
+    int32_t nb;             // boundary sites
+    int32_t xcd_remap;
+    int32_t nontemporal;
+    int32_t clock_in;       // clock slot read this step; the other is written
+    double omega;           // 1 / tau
+    const int32_t* bsite;
+    const uint32_t* bwall;  // elastic wall link mask | inst << 19
+    const uint32_t* bio;    // iolet link mask | iolet slot << 19
+    const int32_t* bk;      // stiffness index
+    const float* bw;        // iolet profile weight
+    const InstParams* ip;
+    const IoletParams* iop;
+    const double* kinv;     // 1 / k per stiffness index
+    int64_t* clock;         // [2] steps executed before the current one
+};
+
+struct FieldArgs {
+    const void* A;
+    const void* nbr;
+    int64_t np;
+    int32_t first;          // first site of the instance
+    int32_t n;              // sites of the instance
+    double omega;
+    double* rho;            // n
+    double* u;              // 3n
+};
+
+struct WallArgs {
+    const void* A;
+    const void* nbr;
+    int64_t np;
+    int32_t first;          // first site of the instance
+    int32_t nw;             // wall sites of the instance
+    const int32_t* wsite;   // wall-site list of the instance
+    const double* wnormal;  // 3 per wall site
+    const int32_t* wk;      // stiffness index per wall site
+    double omega;
+    double stress_fac;      // 1 - 1/(2 tau)
+    double dp0;
+    int32_t elastic;
+    const double* kinv;
+    double* wss;            // n (indexed by site - first)
+    float* dr;              // n
+};
+
+struct InitArgs {
+    void* A;
+    const void* nbr;
+    int64_t np;
+    int32_t first, n;
+    const double* rho;      // n, or NULL
+    const double* u;        // 3n, or NULL
+    const float* rho_u;     // 4n (device float input), or NULL
+    const double* f;        // 19n populations (checkpoint write), or NULL
+};
+
+struct PopArgs {
+    const void* A;
+    const void* nbr;
+    int64_t np;
+    int32_t first, n;
+    double* f;              // 19n
+};
+
+struct DeltaArgs {
+    const void* A;
+    const void* nbr;
+    int64_t np;
+    int32_t first, n;
+    double dp0;             // 1/3 - P0
+    float* snap;            // 4n: ux, uy, uz, p - 1/3 of the previous call
+    int32_t has_snap;
+    unsigned int* maxes;    // 4: max|du|, max|u|, max|dp|, max|p - P0| (float bits)
+};
+
+// Launchers (kernels.hip).  dtype: enum lbm_dtype; ibits: 16 or 32.
+hipError_t launch_step(int dtype, int ibits, const StepArgs& a, int block, hipStream_t s);
+hipError_t launch_fields(int dtype, int ibits, const FieldArgs& a, hipStream_t s);
+hipError_t launch_wall(int dtype, int ibits, const WallArgs& a, hipStream_t s);
+hipError_t launch_init(int dtype, int ibits, const InitArgs& a, hipStream_t s);
+hipError_t launch_read_pop(int dtype, int ibits, const PopArgs& a, hipStream_t s);
+hipError_t launch_delta(int dtype, int ibits, const DeltaArgs& a, hipStream_t s);
+hipError_t launch_zero_u32(unsigned int* p, int n, hipStream_t s);
+
+}  // namespace lbm

@@ -1,0 +1,902 @@
+// Native runtime and C ABI of the library (declared in include/lbm.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "builder.hpp"
+#include "d3q19.hpp"
+#include "kernels.hpp"
+
+using namespace lbm;
+
+namespace {
+
+thread_local std::string g_last_error = "";
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+struct InstState {
+    int mode = LBM_WALL_BOUNCEBACK;
+    double F = 0.0, P0 = 1.0 / 3.0;
+    std::vector<double> k;      // per segment
+    int64_t t0 = 0;
+    std::vector<IoletParams> iolets;
+    std::vector<uint8_t> iolet_set;
+    DevBuf snap;                // periodicity snapshot
+    bool has_snap = false;
+};
+
+struct TuneKey {
+    int64_t n, nb;
+    int dtype;
+    bool operator<(const TuneKey& o) const {
+        return std::tie(n, nb, dtype) < std::tie(o.n, o.nb, o.dtype);
+    }
+};
+struct TuneVal {
+    int block, ibits, xcd, nt;
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneVal> g_tune_cache;
+
+constexpr int GRAPH_STEPS = 128;  // even
+
+}  // namespace
+
+struct lbm_ctx {
+    std::string err;
+    Plan plan;
+    int dtype = LBM_F32;
+    double tau = 1.0;
+    size_t esize = 4;
+    int64_t np = 0;
+    std::vector<InstState> ist;
+    std::vector<int> seg_off, iolet_off;
+    int n_iolet_slots = 0, n_k = 0;
+    // device memory
+    std::vector<DevBuf> owned;
+    void* buf[2] = {nullptr, nullptr};
+    void* nbr32 = nullptr;
+    void* nbr16 = nullptr;
+    bool have16 = false;
+    int32_t* bsite = nullptr;
+    uint32_t* bwall = nullptr;
+    uint32_t* bio = nullptr;
+    int32_t* bk = nullptr;
+    float* bw = nullptr;
+    int64_t nb = 0, nb_cap = 0;
+    int32_t* wsite = nullptr;
+    double* wnormal = nullptr;
+    int32_t* wk = nullptr;
+    InstParams* ip = nullptr;
+    IoletParams* iop = nullptr;
+    double* kinv = nullptr;
+    int64_t* clock = nullptr;
+    unsigned int* maxes = nullptr;
+    DevBuf scratch;
+    // state
+    int64_t step = 0;
+    bool tables_dirty = true, params_dirty = true;
+    // launch configuration
+    int block = 256, ibits = 32, use_graph = 1, xcd = 1, nt = 0;
+    hipStream_t stream = nullptr;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};  // by buffer parity at start
+    int64_t device_bytes = 0;
+};
+
+namespace {
+
+int fail(lbm_ctx* c, int code, const char* fmt, ...) {
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (c)
+        c->err = buf;
+    else
+        g_last_error = buf;
+    return code;
+}
+
+#define HIP_TRY(ctx, expr)                                                                  \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail((ctx), LBM_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+int dalloc(lbm_ctx* c, void** p, size_t bytes) {
+    *p = nullptr;
+    if (bytes == 0) bytes = 256;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c, LBM_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    }
+    c->owned.push_back({*p, bytes});
+    c->device_bytes += (int64_t)bytes;
+    return LBM_OK;
+}
+
+void dfree(lbm_ctx* c, void* p) {
+    if (!p) return;
+    for (size_t i = 0; i < c->owned.size(); ++i)
+        if (c->owned[i].p == p) {
+            c->device_bytes -= (int64_t)c->owned[i].bytes;
+            c->owned.erase(c->owned.begin() + i);
+            break;
+        }
+    (void)hipFree(p);
+}
+
+int ensure_scratch(lbm_ctx* c, size_t bytes) {
+    if (c->scratch.bytes >= bytes) return LBM_OK;
+    dfree(c, c->scratch.p);
+    c->scratch = DevBuf();
+    int rc = dalloc(c, &c->scratch.p, bytes);
+    if (rc) return rc;
+    c->scratch.bytes = bytes;
+    return LBM_OK;
+}
+
+void drop_graphs(lbm_ctx* c) {
+    for (auto& g : c->graph)
+        if (g) {
+            (void)hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+}
+
+std::vector<int> modes(const lbm_ctx* c) {
+    std::vector<int> m(c->ist.size());
+    for (size_t i = 0; i < m.size(); ++i) m[i] = c->ist[i].mode;
+    return m;
+}
+
+int upload(lbm_ctx* c, void* dst, const void* src, size_t bytes) {
+    if (!bytes) return LBM_OK;
+    HIP_TRY(c, hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+// Rebuilds the device neighbour tables and boundary list after a change of
+// wall mode (bounce-back links redirect inside the update; elastic links go
+// through the boundary pass).
+int sync_tables(lbm_ctx* c) {
+    if (!c->tables_dirty) return LBM_OK;
+    const std::vector<int> m = modes(c);
+    {
+        std::vector<int32_t> t32;
+        build_device_nbr<int32_t>(c->plan, m, c->np, t32);
+        int rc = upload(c, c->nbr32, t32.data(), t32.size() * 4);
+        if (rc) return rc;
+    }
+    if (c->have16) {
+        std::vector<int16_t> t16;
+        build_device_nbr<int16_t>(c->plan, m, c->np, t16);
+        int rc = upload(c, c->nbr16, t16.data(), t16.size() * 2);
+        if (rc) return rc;
+    }
+    BoundaryList bl;
+    build_boundary(c->plan, m, c->seg_off, c->iolet_off, bl);
+    const int64_t nb = (int64_t)bl.site.size();
+    if (nb > c->nb_cap) {
+        dfree(c, c->bsite); dfree(c, c->bwall); dfree(c, c->bio); dfree(c, c->bk); dfree(c, c->bw);
+        int rc = 0;
+        rc |= dalloc(c, (void**)&c->bsite, nb * 4);
+        rc |= dalloc(c, (void**)&c->bwall, nb * 4);
+        rc |= dalloc(c, (void**)&c->bio, nb * 4);
+        rc |= dalloc(c, (void**)&c->bk, nb * 4);
+        rc |= dalloc(c, (void**)&c->bw, nb * 4);
+        if (rc) return LBM_ENOMEM;
+        c->nb_cap = nb;
+    }
+    c->nb = nb;
+    int rc = upload(c, c->bsite, bl.site.data(), nb * 4);
+    rc = rc ? rc : upload(c, c->bwall, bl.wall.data(), nb * 4);
+    rc = rc ? rc : upload(c, c->bio, bl.io.data(), nb * 4);
+    rc = rc ? rc : upload(c, c->bk, bl.kidx.data(), nb * 4);
+    rc = rc ? rc : upload(c, c->bw, bl.weight.data(), nb * 4);
+    if (rc) return rc;
+    c->tables_dirty = false;
+    drop_graphs(c);
+    return LBM_OK;
+}
+
+int sync_params(lbm_ctx* c) {
+    if (!c->params_dirty) return LBM_OK;
+    const int ni = (int)c->ist.size();
+    std::vector<InstParams> ip(ni);
+    std::vector<IoletParams> iop(std::max(1, c->n_iolet_slots));
+    std::vector<double> kinv(std::max(1, c->n_k), 1.0);
+    for (int k = 0; k < ni; ++k) {
+        const InstState& s = c->ist[k];
+        ip[k].F = s.F;
+        ip[k].dp0 = 1.0 / 3.0 - s.P0;
+        ip[k].t0 = s.t0;
+        ip[k].elastic = s.mode == LBM_WALL_ELASTIC;
+        ip[k].pad = 0;
+        for (size_t j = 0; j < s.k.size(); ++j) kinv[c->seg_off[k] + j] = 1.0 / s.k[j];
+        for (size_t j = 0; j < s.iolets.size(); ++j) iop[c->iolet_off[k] + j] = s.iolets[j];
+    }
+    int rc = upload(c, c->ip, ip.data(), ip.size() * sizeof(InstParams));
+    rc = rc ? rc : upload(c, c->iop, iop.data(), iop.size() * sizeof(IoletParams));
+    rc = rc ? rc : upload(c, c->kinv, kinv.data(), kinv.size() * sizeof(double));
+    if (rc) return rc;
+    c->params_dirty = false;
+    return LBM_OK;
+}
+
+int check_ready(lbm_ctx* c) {
+    for (size_t k = 0; k < c->ist.size(); ++k) {
+        const InstanceGeom& g = c->plan.inst[k];
+        for (int id = 0; id < g.n_iolet; ++id)
+            if (g.iolet_used[id] && !c->ist[k].iolet_set[id])
+                return fail(c, LBM_ESTATE, "instance %zu: iolet %d is used but has no parameters",
+                            k, id);
+    }
+    int rc = sync_tables(c);
+    return rc ? rc : sync_params(c);
+}
+
+const void* nbr_ptr(const lbm_ctx* c) { return c->ibits == 16 ? c->nbr16 : c->nbr32; }
+
+StepArgs step_args(const lbm_ctx* c, int parity) {
+    StepArgs a;
+    a.A = c->buf[parity];
+    a.B = c->buf[parity ^ 1];
+    a.nbr = nbr_ptr(c);
+    a.np = c->np;
+    a.n = (int32_t)c->plan.N;
+    a.n_int_blocks = (int32_t)((c->plan.N + c->block - 1) / c->block);
+    a.nb = (int32_t)c->nb;
+    a.xcd_remap = c->xcd;
+    a.nontemporal = c->nt;
+    a.clock_in = parity;
+    a.omega = 1.0 / c->tau;
+    a.bsite = c->bsite;
+    a.bwall = c->bwall;
+    a.bio = c->bio;
+    a.bk = c->bk;
+    a.bw = c->bw;
+    a.ip = c->ip;
+    a.iop = c->iop;
+    a.kinv = c->kinv;
+    a.clock = c->clock;
+    return a;
+}
+
+int enqueue_step(lbm_ctx* c) {
+    const int parity = (int)(c->step & 1);
+    hipError_t e = launch_step(c->dtype, c->ibits, step_args(c, parity), c->block, c->stream);
+    if (e != hipSuccess) return fail(c, LBM_EDEVICE, "update launch failed: %s", hipGetErrorString(e));
+    c->step += 1;
+    return LBM_OK;
+}
+
+int get_graph(lbm_ctx* c, int parity, hipGraphExec_t* out) {
+    if (c->graph[parity]) {
+        *out = c->graph[parity];
+        return LBM_OK;
+    }
+    hipGraph_t g = nullptr;
+    HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t le = hipSuccess;
+    for (int k = 0; k < GRAPH_STEPS && le == hipSuccess; ++k)
+        le = launch_step(c->dtype, c->ibits, step_args(c, (parity + k) & 1), c->block, c->stream);
+    hipError_t ce = hipStreamEndCapture(c->stream, &g);
+    if (le != hipSuccess || ce != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(c, LBM_EDEVICE, "graph capture failed: %s",
+                    hipGetErrorString(le != hipSuccess ? le : ce));
+    }
+    hipGraphExec_t ex = nullptr;
+    hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) return fail(c, LBM_EDEVICE, "graph instantiate failed: %s", hipGetErrorString(ie));
+    c->graph[parity] = ex;
+    *out = ex;
+    return LBM_OK;
+}
+
+int run_steps(lbm_ctx* c, int64_t n) {
+    while (n > 0) {
+        if (c->use_graph && n >= GRAPH_STEPS) {
+            hipGraphExec_t ex;
+            int rc = get_graph(c, (int)(c->step & 1), &ex);
+            if (rc) return rc;
+            HIP_TRY(c, hipGraphLaunch(ex, c->stream));
+            c->step += GRAPH_STEPS;
+            n -= GRAPH_STEPS;
+        } else {
+            int rc = enqueue_step(c);
+            if (rc) return rc;
+            n -= 1;
+        }
+    }
+    return LBM_OK;
+}
+
+int check_inst(lbm_ctx* c, int inst) {
+    if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+    if (inst < 0 || inst >= (int)c->ist.size())
+        return fail(c, LBM_EINVAL, "instance %d out of range [0, %zu)", inst, c->ist.size());
+    return LBM_OK;
+}
+
+size_t elem_size(int dtype) {
+    switch (dtype) {
+        case LBM_F64: return 8;
+        case LBM_F32: return 4;
+        case LBM_F16DEV:
+        case LBM_BF16DEV: return 2;
+    }
+    return 0;
+}
+
+int init_instance(lbm_ctx* c, int inst, const double* rho, const double* u, const float* rho_u_dev,
+                  const double* f) {
+    int rc = sync_tables(c);
+    if (rc) return rc;
+    const InstanceGeom& g = c->plan.inst[inst];
+    const int64_t n = g.n;
+    InitArgs a;
+    a.A = c->buf[c->step & 1];
+    a.nbr = nbr_ptr(c);
+    a.np = c->np;
+    a.first = (int32_t)g.offset;
+    a.n = (int32_t)n;
+    a.rho = nullptr;
+    a.u = nullptr;
+    a.rho_u = rho_u_dev;
+    a.f = nullptr;
+    size_t need = 0;
+    if (f) need = (size_t)n * Q * 8;
+    else need = (size_t)n * 4 * 8;
+    rc = ensure_scratch(c, need);
+    if (rc) return rc;
+    double* s = (double*)c->scratch.p;
+    if (f) {
+        HIP_TRY(c, hipMemcpyAsync(s, f, (size_t)n * Q * 8, hipMemcpyHostToDevice, c->stream));
+        a.f = s;
+    } else if (!rho_u_dev) {
+        if (rho) {
+            HIP_TRY(c, hipMemcpyAsync(s, rho, (size_t)n * 8, hipMemcpyHostToDevice, c->stream));
+            a.rho = s;
+        }
+        if (u) {
+            HIP_TRY(c, hipMemcpyAsync(s + n, u, (size_t)n * 24, hipMemcpyHostToDevice, c->stream));
+            a.u = s + n;
+        }
+    }
+    hipError_t e = launch_init(c->dtype, c->ibits, a, c->stream);
+    if (e != hipSuccess) return fail(c, LBM_EDEVICE, "init launch failed: %s", hipGetErrorString(e));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lbm_last_error(const lbm_ctx* ctx) {
+    return ctx ? ctx->err.c_str() : g_last_error.c_str();
+}
+
+int lbm_plan_export(const lbm_instance_desc* inst, int n_inst, const int* wall_mode,
+                    int64_t* counts, int32_t* nbr, int32_t* boundary, uint32_t* bmask) {
+    Plan p;
+    std::string e = build_plan(inst, n_inst, p);
+    if (!e.empty()) return fail(nullptr, LBM_EINVAL, "%s", e.c_str());
+    std::vector<int> m(n_inst, LBM_WALL_BOUNCEBACK), so(n_inst, 0), io(n_inst, 0);
+    if (wall_mode)
+        for (int k = 0; k < n_inst; ++k) m[k] = wall_mode[k];
+    BoundaryList bl;
+    build_boundary(p, m, so, io, bl);
+    if (counts) {
+        counts[0] = p.N;
+        counts[1] = (int64_t)bl.site.size();
+        counts[2] = (int64_t)p.wall_site.size();
+        counts[3] = p.n_wall_links;
+        counts[4] = p.n_iolet_links;
+        counts[5] = p.max_abs_offset;
+    }
+    if (nbr) {
+        std::vector<int32_t> t;
+        build_device_nbr<int32_t>(p, m, p.N, t);
+        std::memcpy(nbr, t.data(), t.size() * 4);
+    }
+    if (boundary) std::memcpy(boundary, bl.site.data(), bl.site.size() * 4);
+    if (bmask)
+        for (size_t j = 0; j < bl.site.size(); ++j)
+            bmask[j] = (bl.wall[j] & 0x7FFFEu) | (bl.io[j] & 0x7FFFEu);
+    return LBM_OK;
+}
+
+int lbm_create_geometry(lbm_ctx** out, const lbm_instance_desc* inst, int n_inst, int dtype,
+                        double tau) {
+    if (!out) return fail(nullptr, LBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!(tau > 0.5)) return fail(nullptr, LBM_EINVAL, "tau must exceed 1/2 (got %g)", tau);
+    if (elem_size(dtype) == 0) return fail(nullptr, LBM_EINVAL, "unknown dtype %d", dtype);
+    if (n_inst <= 0 || n_inst > 8191) return fail(nullptr, LBM_EINVAL, "n_inst out of range");
+    lbm_ctx* c = new (std::nothrow) lbm_ctx();
+    if (!c) return fail(nullptr, LBM_ENOMEM, "out of host memory");
+    std::string e = build_plan(inst, n_inst, c->plan);
+    if (!e.empty()) {
+        delete c;
+        return fail(nullptr, LBM_EINVAL, "%s", e.c_str());
+    }
+    c->dtype = dtype;
+    c->tau = tau;
+    c->esize = elem_size(dtype);
+    c->np = (c->plan.N + 255) / 256 * 256;
+    c->ist.resize(n_inst);
+    c->seg_off.resize(n_inst);
+    c->iolet_off.resize(n_inst);
+    int so = 0, io = 0;
+    for (int k = 0; k < n_inst; ++k) {
+        const InstanceGeom& g = c->plan.inst[k];
+        InstState& s = c->ist[k];
+        s.k.assign(g.n_seg, 1.0);
+        s.iolets.assign(std::max(g.n_iolet, 0), IoletParams());
+        s.iolet_set.assign(std::max(g.n_iolet, 0), 0);
+        c->seg_off[k] = so;
+        c->iolet_off[k] = io;
+        so += g.n_seg;
+        io += std::max(g.n_iolet, 0);
+    }
+    c->n_k = so;
+    c->n_iolet_slots = io;
+    if (io >= 8192) {
+        delete c;
+        return fail(nullptr, LBM_EINVAL, "too many iolets (%d) in one context", io);
+    }
+    c->have16 = c->plan.max_abs_offset <= Sentinel<int16_t>::MAXABS - 1;
+    c->ibits = c->have16 ? 16 : 32;
+    hipError_t he = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    if (he != hipSuccess) {
+        delete c;
+        return fail(nullptr, LBM_EDEVICE, "hipStreamCreate failed: %s", hipGetErrorString(he));
+    }
+    int rc = 0;
+    const size_t pop_bytes = (size_t)Q * c->np * c->esize;
+    rc = rc ? rc : dalloc(c, &c->buf[0], pop_bytes);
+    rc = rc ? rc : dalloc(c, &c->buf[1], pop_bytes);
+    rc = rc ? rc : dalloc(c, &c->nbr32, (size_t)18 * c->np * 4);
+    if (c->have16) rc = rc ? rc : dalloc(c, &c->nbr16, (size_t)18 * c->np * 2);
+    const int64_t nw = (int64_t)c->plan.wall_site.size();
+    rc = rc ? rc : dalloc(c, (void**)&c->wsite, nw * 4);
+    rc = rc ? rc : dalloc(c, (void**)&c->wnormal, nw * 24);
+    rc = rc ? rc : dalloc(c, (void**)&c->wk, nw * 4);
+    rc = rc ? rc : dalloc(c, (void**)&c->ip, n_inst * sizeof(InstParams));
+    rc = rc ? rc : dalloc(c, (void**)&c->iop, std::max(1, io) * sizeof(IoletParams));
+    rc = rc ? rc : dalloc(c, (void**)&c->kinv, std::max(1, so) * sizeof(double));
+    rc = rc ? rc : dalloc(c, (void**)&c->clock, 2 * sizeof(int64_t));
+    rc = rc ? rc : dalloc(c, (void**)&c->maxes, 4 * sizeof(unsigned int));
+    if (rc) {
+        g_last_error = c->err;
+        lbm_destroy(c);
+        return rc;
+    }
+    // wall-site arrays (fixed by the geometry)
+    std::vector<int32_t> wk(nw);
+    for (int64_t j = 0; j < nw; ++j) {
+        const int32_t x = c->plan.wall_site[j];
+        const uint32_t k = c->plan.site_inst[x];
+        wk[j] = c->seg_off[k] + c->plan.site_seg[x];
+    }
+    const int64_t zero2[2] = {0, 0};
+    rc = rc ? rc : upload(c, c->wsite, c->plan.wall_site.data(), nw * 4);
+    rc = rc ? rc : upload(c, c->wnormal, c->plan.wall_normal.data(), nw * 24);
+    rc = rc ? rc : upload(c, c->wk, wk.data(), nw * 4);
+    rc = rc ? rc : upload(c, c->clock, zero2, sizeof(zero2));
+    // padding / unused slots start at zero deviation
+    if (!rc) {
+        hipError_t z0 = hipMemsetAsync(c->buf[0], 0, pop_bytes, c->stream);
+        hipError_t z1 = hipMemsetAsync(c->buf[1], 0, pop_bytes, c->stream);
+        if (z0 != hipSuccess || z1 != hipSuccess) rc = fail(c, LBM_EDEVICE, "hipMemset failed");
+    }
+    for (int k = 0; k < n_inst && !rc; ++k) rc = init_instance(c, k, nullptr, nullptr, nullptr, nullptr);
+    rc = rc ? rc : sync_params(c);
+    if (rc) {
+        g_last_error = c->err;
+        lbm_destroy(c);
+        return rc;
+    }
+    *out = c;
+    return LBM_OK;
+}
+
+int lbm_destroy(lbm_ctx* c) {
+    if (!c) return LBM_OK;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    drop_graphs(c);
+    for (auto& b : c->owned) (void)hipFree(b.p);
+    c->owned.clear();
+    if (c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+    return LBM_OK;
+}
+
+int lbm_set_wall_params(lbm_ctx* c, int inst, int mode, double F, double P0,
+                        const double* k_per_segment, int n_seg) {
+    int rc = check_inst(c, inst);
+    if (rc) return rc;
+    if (mode != LBM_WALL_BOUNCEBACK && mode != LBM_WALL_ELASTIC)
+        return fail(c, LBM_EINVAL, "unknown wall mode %d", mode);
+    if (!(F >= 0.0 && F < 1.0)) return fail(c, LBM_EINVAL, "F must lie in [0, 1) (got %g)", F);
+    if (!std::isfinite(P0)) return fail(c, LBM_EINVAL, "P0 must be finite");
+    const InstanceGeom& g = c->plan.inst[inst];
+    if (n_seg < g.n_seg || !k_per_segment)
+        return fail(c, LBM_EINVAL, "instance %d uses %d segments, got %d stiffness values", inst,
+                    g.n_seg, n_seg);
+    for (int s = 0; s < g.n_seg; ++s)
+        if (!(k_per_segment[s] > 0.0))
+            return fail(c, LBM_EINVAL, "stiffness of segment %d must be > 0 (got %g)", s,
+                        k_per_segment[s]);
+    InstState& s = c->ist[inst];
+    if (s.mode != mode) c->tables_dirty = true;
+    s.mode = mode;
+    s.F = F;
+    s.P0 = P0;
+    for (int j = 0; j < g.n_seg; ++j) s.k[j] = k_per_segment[j];
+    c->params_dirty = true;
+    return LBM_OK;
+}
+
+int lbm_set_iolet(lbm_ctx* c, int inst, int id, int kind, double a0, double amp, double period,
+                  double phase, const double* dir) {
+    int rc = check_inst(c, inst);
+    if (rc) return rc;
+    InstState& s = c->ist[inst];
+    if (id < 0 || id >= (int)s.iolets.size())
+        return fail(c, LBM_EINVAL, "instance %d has no iolet %d adjacent to a fluid site", inst, id);
+    if (kind != LBM_IOLET_DENSITY && kind != LBM_IOLET_VELOCITY)
+        return fail(c, LBM_EINVAL, "unknown iolet kind %d", kind);
+    if (!std::isfinite(a0) || !std::isfinite(amp) || !std::isfinite(phase))
+        return fail(c, LBM_EINVAL, "iolet parameters must be finite");
+    if (amp != 0.0 && !(period > 0.0)) return fail(c, LBM_EINVAL, "period must be > 0 when amp != 0");
+    if (kind == LBM_IOLET_DENSITY && !(a0 > 0.0)) return fail(c, LBM_EINVAL, "density must be > 0");
+    IoletParams q{};
+    q.a0 = a0;
+    q.amp = amp;
+    q.inv_period = amp != 0.0 ? 1.0 / period : 0.0;
+    q.phase = phase;
+    q.kind = kind;
+    if (kind == LBM_IOLET_VELOCITY) {
+        if (!dir) return fail(c, LBM_EINVAL, "velocity iolet needs a direction");
+        const double nn = std::sqrt(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
+        if (!(nn > 0.0)) return fail(c, LBM_EINVAL, "direction must be non-zero");
+        for (int a = 0; a < 3; ++a) q.dir[a] = dir[a];
+    }
+    s.iolets[id] = q;
+    s.iolet_set[id] = 1;
+    c->params_dirty = true;
+    return LBM_OK;
+}
+
+int lbm_init_fields(lbm_ctx* c, int inst, const double* rho, const double* u) {
+    int rc = check_inst(c, inst);
+    if (rc) return rc;
+    rc = init_instance(c, inst, rho, u, nullptr, nullptr);
+    if (rc) return rc;
+    c->ist[inst].t0 = c->step;
+    c->ist[inst].has_snap = false;
+    c->params_dirty = true;
+    return sync_params(c);
+}
+
+int lbm_init_fields_device(lbm_ctx* c, int inst, const float* rho_u_dev) {
+    int rc = check_inst(c, inst);
+    if (rc) return rc;
+    if (!rho_u_dev) return fail(c, LBM_EINVAL, "rho_u_dev is NULL");
+    rc = init_instance(c, inst, nullptr, nullptr, rho_u_dev, nullptr);
+    if (rc) return rc;
+    c->ist[inst].t0 = c->step;
+    c->ist[inst].has_snap = false;
+    c->params_dirty = true;
+    return sync_params(c);
+}
+
+int lbm_step(lbm_ctx* c, int64_t n) {
+    if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+    if (n < 0) return fail(c, LBM_EINVAL, "n must be >= 0");
+    int rc = check_ready(c);
+    if (rc) return rc;
+    return run_steps(c, n);
+}
+
+int lbm_sync(lbm_ctx* c) {
+    if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+int lbm_get_stream(lbm_ctx* c, void** stream) {
+    if (!c || !stream) return fail(c, LBM_EINVAL, "NULL argument");
+    *stream = (void*)c->stream;
+    return LBM_OK;
+}
+
+int lbm_time_steps(lbm_ctx* c, int64_t n, double* ms) {
+    if (!c || !ms) return fail(c, LBM_EINVAL, "NULL argument");
+    int rc = check_ready(c);
+    if (rc) return rc;
+    if (c->use_graph && n >= GRAPH_STEPS) {  // capture outside the timed region
+        hipGraphExec_t ex;
+        rc = get_graph(c, (int)(c->step & 1), &ex);
+        if (rc) return rc;
+    }
+    hipEvent_t e0, e1;
+    HIP_TRY(c, hipEventCreate(&e0));
+    HIP_TRY(c, hipEventCreate(&e1));
+    HIP_TRY(c, hipEventRecord(e0, c->stream));
+    rc = run_steps(c, n);
+    HIP_TRY(c, hipEventRecord(e1, c->stream));
+    HIP_TRY(c, hipEventSynchronize(e1));
+    float t = 0;
+    HIP_TRY(c, hipEventElapsedTime(&t, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms = t;
+    return rc;
+}
+
+int lbm_read_fields(lbm_ctx* c, int inst, double* rho, double* u, double* wss, float* wall_dr) {
+    int rc = check_inst(c, inst);
+    if (rc) return rc;
+    rc = sync_tables(c);
+    rc = rc ? rc : sync_params(c);
+    if (rc) return rc;
+    const InstanceGeom& g = c->plan.inst[inst];
+    const int64_t n = g.n;
+    rc = ensure_scratch(c, (size_t)n * (8 * 5) + (size_t)n * 4 + 256);
+    if (rc) return rc;
+    double* s_rho = (double*)c->scratch.p;
+    double* s_u = s_rho + n;
+    double* s_wss = s_u + 3 * n;
+    float* s_dr = (float*)(s_wss + n);
+    const void* A = c->buf[c->step & 1];
+    FieldArgs fa{A, nbr_ptr(c), c->np, (int32_t)g.offset, (int32_t)n, 1.0 / c->tau, s_rho, s_u};
+    hipError_t e = launch_fields(c->dtype, c->ibits, fa, c->stream);
+    if (e != hipSuccess) return fail(c, LBM_EDEVICE, "read-out launch failed: %s", hipGetErrorString(e));
+    if (wss || wall_dr) {
+        HIP_TRY(c, hipMemsetAsync(s_wss, 0, (size_t)n * 8, c->stream));
+        HIP_TRY(c, hipMemsetAsync(s_dr, 0, (size_t)n * 4, c->stream));
+        const InstState& st = c->ist[inst];
+        WallArgs wa;
+        wa.A = A;
+        wa.nbr = nbr_ptr(c);
+        wa.np = c->np;
+        wa.first = (int32_t)g.offset;
+        wa.nw = (int32_t)(g.wall_end - g.wall_begin);
+        wa.wsite = c->wsite + g.wall_begin;
+        wa.wnormal = c->wnormal + 3 * g.wall_begin;
+        wa.wk = c->wk + g.wall_begin;
+        wa.omega = 1.0 / c->tau;
+        wa.stress_fac = 1.0 - 1.0 / (2.0 * c->tau);
+        wa.dp0 = 1.0 / 3.0 - st.P0;
+        wa.elastic = st.mode == LBM_WALL_ELASTIC;
+        wa.kinv = c->kinv;
+        wa.wss = s_wss;
+        wa.dr = s_dr;
+        e = launch_wall(c->dtype, c->ibits, wa, c->stream);
+        if (e != hipSuccess) return fail(c, LBM_EDEVICE, "wall read-out launch failed: %s", hipGetErrorString(e));
+    }
+    std::vector<double> hr, hu;
+    double* prho = rho;
+    double* pu = u;
+    if (!prho) { hr.resize(n); prho = hr.data(); }
+    if (!pu) { hu.resize(3 * n); pu = hu.data(); }
+    HIP_TRY(c, hipMemcpyAsync(prho, s_rho, (size_t)n * 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(pu, s_u, (size_t)n * 24, hipMemcpyDeviceToHost, c->stream));
+    if (wss) HIP_TRY(c, hipMemcpyAsync(wss, s_wss, (size_t)n * 8, hipMemcpyDeviceToHost, c->stream));
+    if (wall_dr) HIP_TRY(c, hipMemcpyAsync(wall_dr, s_dr, (size_t)n * 4, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (int64_t k = 0; k < n; ++k)
+        if (!std::isfinite(prho[k]) || !std::isfinite(pu[3 * k]) || !std::isfinite(pu[3 * k + 1]) ||
+            !std::isfinite(pu[3 * k + 2]))
+            return fail(c, LBM_EDIVERGED, "non-finite field at site %lld of instance %d (step %lld)",
+                        (long long)k, inst, (long long)c->step);
+    return LBM_OK;
+}
+
+int lbm_read_populations(lbm_ctx* c, int inst, double* f) {
+    int rc = check_inst(c, inst);
+    if (rc) return rc;
+    if (!f) return fail(c, LBM_EINVAL, "f is NULL");
+    rc = sync_tables(c);
+    if (rc) return rc;
+    const InstanceGeom& g = c->plan.inst[inst];
+    rc = ensure_scratch(c, (size_t)g.n * Q * 8);
+    if (rc) return rc;
+    PopArgs a{c->buf[c->step & 1], nbr_ptr(c), c->np, (int32_t)g.offset, (int32_t)g.n,
+              (double*)c->scratch.p};
+    hipError_t e = launch_read_pop(c->dtype, c->ibits, a, c->stream);
+    if (e != hipSuccess) return fail(c, LBM_EDEVICE, "launch failed: %s", hipGetErrorString(e));
+    HIP_TRY(c, hipMemcpyAsync(f, c->scratch.p, (size_t)g.n * Q * 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+int lbm_write_populations(lbm_ctx* c, int inst, const double* f) {
+    int rc = check_inst(c, inst);
+    if (rc) return rc;
+    if (!f) return fail(c, LBM_EINVAL, "f is NULL");
+    return init_instance(c, inst, nullptr, nullptr, nullptr, f);
+}
+
+int lbm_cycle_delta(lbm_ctx* c, int inst, double* delta_u, double* delta_p) {
+    int rc = check_inst(c, inst);
+    if (rc) return rc;
+    rc = sync_tables(c);
+    if (rc) return rc;
+    InstState& st = c->ist[inst];
+    const InstanceGeom& g = c->plan.inst[inst];
+    if (!st.snap.p) {
+        rc = dalloc(c, &st.snap.p, (size_t)g.n * 16);
+        if (rc) return rc;
+        st.snap.bytes = (size_t)g.n * 16;
+    }
+    hipError_t e = launch_zero_u32(c->maxes, 4, c->stream);
+    if (e != hipSuccess) return fail(c, LBM_EDEVICE, "launch failed: %s", hipGetErrorString(e));
+    DeltaArgs a{c->buf[c->step & 1], nbr_ptr(c), c->np, (int32_t)g.offset, (int32_t)g.n,
+                1.0 / 3.0 - st.P0, (float*)st.snap.p, st.has_snap ? 1 : 0, c->maxes};
+    e = launch_delta(c->dtype, c->ibits, a, c->stream);
+    if (e != hipSuccess) return fail(c, LBM_EDEVICE, "launch failed: %s", hipGetErrorString(e));
+    unsigned int m[4];
+    HIP_TRY(c, hipMemcpyAsync(m, c->maxes, sizeof(m), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    float v[4];
+    std::memcpy(v, m, sizeof(v));
+    const bool first = !st.has_snap;
+    st.has_snap = true;
+    const double inf = std::numeric_limits<double>::infinity();
+    if (delta_u) *delta_u = first ? inf : (v[1] > 0 ? v[0] / v[1] : (v[0] > 0 ? inf : 0.0));
+    if (delta_p) *delta_p = first ? inf : (v[3] > 0 ? v[2] / v[3] : (v[2] > 0 ? inf : 0.0));
+    if (!std::isfinite(v[0]) || !std::isfinite(v[1]))
+        return fail(c, LBM_EDIVERGED, "non-finite velocity in instance %d", inst);
+    return LBM_OK;
+}
+
+int lbm_get_info(const lbm_ctx* c, lbm_info* info) {
+    if (!c || !info) return fail(nullptr, LBM_EINVAL, "NULL argument");
+    std::memset(info, 0, sizeof(*info));
+    info->n_sites = c->plan.N;
+    info->n_boundary = c->nb;
+    info->n_wall_sites = (int64_t)c->plan.wall_site.size();
+    info->n_wall_links = c->plan.n_wall_links;
+    info->n_iolet_links = c->plan.n_iolet_links;
+    info->step = c->step;
+    info->n_instances = (int32_t)c->ist.size();
+    info->dtype = c->dtype;
+    info->index_bits = c->ibits;
+    info->block_size = c->block;
+    info->use_graph = c->use_graph;
+    info->xcd_remap = c->xcd;
+    info->nontemporal = c->nt;
+    info->bytes_per_site_algorithmic = 2.0 * Q * (double)c->esize;
+    const double N = (double)std::max<int64_t>(1, c->plan.N);
+    info->bytes_per_site_model = 2.0 * Q * (double)c->esize + 18.0 * (c->ibits / 8) +
+                                 (double)c->nb / N * (20.0 + 18.0 * (c->ibits / 8));
+    info->device_bytes = c->device_bytes;
+    return LBM_OK;
+}
+
+int lbm_instance_sites(const lbm_ctx* c, int inst, int64_t* n) {
+    if (!c || !n) return fail(nullptr, LBM_EINVAL, "NULL argument");
+    if (inst < 0 || inst >= (int)c->ist.size()) return fail(nullptr, LBM_EINVAL, "instance out of range");
+    *n = c->plan.inst[inst].n;
+    return LBM_OK;
+}
+
+int lbm_set_launch(lbm_ctx* c, int block_size, int index_bits, int use_graph, int xcd_remap,
+                   int nontemporal) {
+    if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+    if (block_size != -1 && block_size != 64 && block_size != 128 && block_size != 256 &&
+        block_size != 512 && block_size != 1024)
+        return fail(c, LBM_EINVAL, "block size %d not supported", block_size);
+    if (index_bits != -1 && index_bits != 16 && index_bits != 32)
+        return fail(c, LBM_EINVAL, "index_bits must be 16 or 32");
+    if (index_bits == 16 && !c->have16)
+        return fail(c, LBM_EINVAL, "a neighbour offset exceeds the 16-bit range (max %lld)",
+                    (long long)c->plan.max_abs_offset);
+    if (block_size != -1) c->block = block_size;
+    if (index_bits != -1) c->ibits = index_bits;
+    if (use_graph != -1) c->use_graph = use_graph ? 1 : 0;
+    if (xcd_remap != -1) c->xcd = xcd_remap ? 1 : 0;
+    if (nontemporal != -1) c->nt = nontemporal ? 1 : 0;
+    drop_graphs(c);
+    return LBM_OK;
+}
+
+int lbm_autotune(lbm_ctx* c, int steps_per_trial, double* best_rate) {
+    if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+    if (steps_per_trial < 2) return fail(c, LBM_EINVAL, "steps_per_trial must be >= 2");
+    int rc = check_ready(c);
+    if (rc) return rc;
+    const TuneKey key{c->plan.N, c->nb, c->dtype};
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end() && !best_rate) {
+            const TuneVal& v = it->second;
+            return lbm_set_launch(c, v.block, v.ibits, -1, v.xcd, v.nt);
+        }
+    }
+    // save the state: both buffers and the clock
+    const size_t pop_bytes = (size_t)Q * c->np * c->esize;
+    void* save0 = nullptr;
+    void* save1 = nullptr;
+    rc = dalloc(c, &save0, pop_bytes);
+    rc = rc ? rc : dalloc(c, &save1, pop_bytes);
+    if (rc) return rc;
+    int64_t clock_save[2];
+    HIP_TRY(c, hipMemcpyAsync(save0, c->buf[0], pop_bytes, hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(save1, c->buf[1], pop_bytes, hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(clock_save, c->clock, sizeof(clock_save), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    const int64_t step_save = c->step;
+    const int old_block = c->block, old_ibits = c->ibits, old_xcd = c->xcd, old_nt = c->nt;
+    TuneVal best{old_block, old_ibits, old_xcd, old_nt};
+    double best_ms = std::numeric_limits<double>::infinity();
+    const int blocks[] = {128, 256, 512, 1024};
+    const int ibits_list[] = {16, 32};
+    for (int ib : ibits_list) {
+        if (ib == 16 && !c->have16) continue;
+        for (int bs : blocks)
+            for (int xr = 0; xr < 2; ++xr)
+                for (int ntv = 0; ntv < 2; ++ntv) {
+                    rc = lbm_set_launch(c, bs, ib, -1, xr, ntv);
+                    if (rc) break;
+                    double ms = 0;
+                    rc = run_steps(c, 2);  // warm-up (and graph build)
+                    rc = rc ? rc : lbm_time_steps(c, steps_per_trial, &ms);
+                    if (rc) break;
+                    if (ms < best_ms) {
+                        best_ms = ms;
+                        best = {bs, ib, xr, ntv};
+                    }
+                }
+        if (rc) break;
+    }
+    // restore
+    HIP_TRY(c, hipMemcpyAsync(c->buf[0], save0, pop_bytes, hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->buf[1], save1, pop_bytes, hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->clock, clock_save, sizeof(clock_save), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    dfree(c, save0);
+    dfree(c, save1);
+    c->step = step_save;
+    if (rc) {
+        lbm_set_launch(c, old_block, old_ibits, -1, old_xcd, old_nt);
+        return rc;
+    }
+    rc = lbm_set_launch(c, best.block, best.ibits, -1, best.xcd, best.nt);
+    if (rc) return rc;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[key] = best;
+    }
+    if (best_rate) *best_rate = steps_per_trial / (best_ms * 1e-3);
+    return LBM_OK;
+}
+
+}  // extern "C"

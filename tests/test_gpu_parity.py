@@ -1,0 +1,227 @@
+"""GPU path (through the C ABI) against the FP64 oracle on identical seeded
+inputs.
+
+Tolerances: relative L-infinity error (max |gpu - ref| / max |ref|) on
+velocity (all components) and pressure after 1000 steps <= 1e-5 for FP32
+storage; FP64 storage agrees to rounding (<= 1e-11).  FP16/BF16 deviation
+storage errors are stated (logged) and held to loose bounds that only catch
+gross defects.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2108_08783_amd import inputs
+from paper_2108_08783_amd import lbm
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+LOG = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out",
+                   "parity_errors.jsonl")
+
+
+def record(name, errs, **kw):
+    line = dict(case=name, **errs, **kw)
+    print("PARITY", json.dumps(line), flush=True)
+    if os.path.isdir(os.path.dirname(LOG)):
+        with open(LOG, "a") as f:
+            f.write(json.dumps(line) + "\n")
+
+
+TOL = {"f64": 1e-11, "f32": 1e-5}
+
+
+def run_pair(problem, dtype, steps, launch=None):
+    lat = H.make_lattice([problem], dtype)
+    if launch:
+        lat.set_launch(**launch)
+    orc = H.make_oracle(problem)
+    lat.step(steps)
+    orc.step(steps)
+    g = lat.read_fields(0)
+    r = orc.read()
+    lat.close()
+    return g, r
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("mode", [lbm.BOUNCEBACK, lbm.ELASTIC])
+def test_small_tube_density_driven(dtype, mode):
+    """R=8, L=64 tube, tau=0.8, rho 1.001 / 0.999, 1000 steps."""
+    p = H.poiseuille_problem(mode)
+    g, r = run_pair(p, dtype, 1000)
+    e = H.errors(g, r, P0=p.P0)
+    record(f"tube8_{'elastic' if mode else 'bb'}", e, dtype=dtype, steps=1000)
+    assert e["u"] <= TOL[dtype] and e["p"] <= TOL[dtype]
+    assert e["wss"] <= 10 * TOL[dtype]
+    if mode == lbm.ELASTIC:
+        assert e["dr"] <= 1e-6
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "f16", "bf16"])
+def test_pulsatile_elastic_tube(dtype):
+    """R=12, L=96 elastic tube with a pulsatile parabolic velocity inlet
+    (u0 = 0.02, amplitude 0.5) and a density outlet, 1000 steps."""
+    p = H.tube_problem(12, 96, seed=1)
+    g, r = run_pair(p, dtype, 1000)
+    e = H.errors(g, r, P0=p.P0)
+    record("tube12_pulsatile_elastic", e, dtype=dtype, steps=1000)
+    if dtype in TOL:
+        assert e["u"] <= TOL[dtype] and e["p"] <= TOL[dtype]
+        assert e["wss"] <= 10 * TOL[dtype]
+    else:
+        bound = {"f16": 1e-2, "bf16": 5e-2}[dtype]
+        assert e["u"] <= bound and e["p"] <= bound
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("seed", [1, 2])
+def test_random_boxes_every_link_type(dtype, seed):
+    """Random labels (walls, two iolets, thin gaps, opposite wall pairs),
+    three stiffness segments, random initial state, 60 steps."""
+    p = H.random_box_problem(seed)
+    g, r = run_pair(p, dtype, 60)
+    e = H.errors(g, r, P0=p.P0)
+    record(f"random_box_{seed}", e, dtype=dtype, steps=60)
+    tol = TOL[dtype]
+    assert e["u"] <= 10 * tol and e["p"] <= tol and e["wss"] <= 100 * tol
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_batch_of_uneven_instances(dtype):
+    """Several instances of different size and wall mode in one context,
+    each compared with its own oracle run."""
+    probs = [H.tube_problem(6, 20, seed=3, mode=lbm.BOUNCEBACK),
+             H.tube_problem(5, 33, seed=4),
+             H.random_box_problem(9, shape=(8, 7, 9)),
+             H.tube_problem(7, 15, seed=5, pulsatile=False)]
+    for p in probs:
+        p.tau = 0.8
+    lat = H.make_lattice(probs, dtype)
+    lat.step(300)
+    for k, p in enumerate(probs):
+        o = H.make_oracle(p)
+        o.step(300)
+        e = H.errors(lat.read_fields(k), o.read(), P0=p.P0)
+        record(f"batch_inst{k}", e, dtype=dtype, steps=300)
+        assert e["u"] <= 10 * TOL[dtype] and e["p"] <= TOL[dtype]
+    lat.close()
+
+
+def test_single_site_instances():
+    """Degenerate instances: one fluid voxel enclosed by walls (all links
+    are wall links), bounce-back and elastic, next to a normal tube."""
+    box = inputs.Geometry(labels=np.zeros((3, 3, 3), np.uint8))
+    box.labels[1, 1, 1] = 1
+    rng = np.random.default_rng(3)
+    for mode in (lbm.BOUNCEBACK, lbm.ELASTIC):
+        p = H.Problem(geo=box, tau=0.9, mode=mode, F=0.5, P0=0.3, k=[0.01],
+                      rho0=np.array([1.01]), u0=np.array([[0.01, -0.02, 0.005]]))
+        q = H.tube_problem(4, 6, seed=2)
+        q.tau = 0.9
+        lat = H.make_lattice([p, q], "f64")
+        lat.step(25)
+        o = H.make_oracle(p)
+        o.step(25)
+        e = H.errors(lat.read_fields(0), o.read(), P0=p.P0)
+        record(f"single_site_{mode}", e, dtype="f64", steps=25)
+        assert e["p"] <= 1e-12 and np.abs(lat.read_fields(0)[1] - o.read()[1]).max() <= 1e-14
+        lat.close()
+    del rng
+
+
+def test_launch_configurations_are_bit_identical():
+    """Block size, index width, graph replay, XCD remapping and non-temporal
+    stores change only the schedule, never the arithmetic."""
+    p = H.tube_problem(10, 40, seed=6)
+    ref = None
+    for cfg in [dict(block_size=256, index_bits=32, use_graph=0, xcd_remap=0, nontemporal=0),
+                dict(block_size=64, index_bits=16, use_graph=1, xcd_remap=1, nontemporal=1),
+                dict(block_size=1024, index_bits=16, use_graph=1, xcd_remap=0, nontemporal=0),
+                dict(block_size=512, index_bits=32, use_graph=1, xcd_remap=1, nontemporal=1)]:
+        lat = H.make_lattice([p], "f32")
+        lat.set_launch(**cfg)
+        lat.step(300)
+        f = lat.read_populations(0)
+        lat.close()
+        if ref is None:
+            ref = f
+        else:
+            assert np.array_equal(f, ref), cfg
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16"])
+def test_checkpoint_restart_is_bit_identical(dtype):
+    p = H.tube_problem(6, 24, seed=7, pulsatile=False)
+    a = H.make_lattice([p], dtype)
+    a.step(137)
+    f = a.read_populations(0)
+    b = H.make_lattice([p], dtype)
+    b.write_populations(0, f)
+    assert np.array_equal(b.read_populations(0), f)
+    a.step(263)
+    b.step(263)
+    assert np.array_equal(a.read_populations(0), b.read_populations(0))
+    a.close()
+    b.close()
+
+
+def test_initial_populations_are_equilibrium():
+    import oracle
+    p = H.random_box_problem(4)
+    lat = H.make_lattice([p], "f64")
+    f = lat.read_populations(0)
+    for s in range(0, len(f), 7):
+        assert np.allclose(f[s], oracle.feq(p.rho0[s], p.u0[s]), rtol=0, atol=1e-16)
+    lat.close()
+
+
+def test_divergence_is_reported():
+    p = H.tube_problem(5, 12, seed=8, pulsatile=False)
+    p.iolets[0]["a0"] = 0.9
+    p.tau = 0.501
+    lat = H.make_lattice([p], "f32")
+    lat.step(3000)
+    with pytest.raises(lbm.Diverged):
+        lat.read_fields(0)
+    lat.close()
+
+
+def test_cycle_delta_monitor():
+    p = H.tube_problem(6, 24, seed=9)
+    lat = H.make_lattice([p], "f32")
+    lat.step(50)
+    du, dp = lat.cycle_delta(0)
+    assert np.isinf(du) and np.isinf(dp)
+    du, dp = lat.cycle_delta(0)
+    assert du == 0.0 and dp == 0.0
+    lat.step(40)
+    du, dp = lat.cycle_delta(0)
+    rho1, u1, _, _ = lat.read_fields(0)
+    assert 0 < du < np.inf and 0 < dp < np.inf
+    lat.close()
+
+
+def test_full_size_tube_parity_short_run():
+    """The 1,640,960-site tube (R=32, L=512) in the benchmark's launch
+    configuration (autotuned), from a non-equilibrium state, 24 steps, FP32
+    against the oracle over every site."""
+    p = H.tube_problem(32, 512, seed=1, period=4000.0)
+    rng = np.random.default_rng(12)
+    n = p.geo.n_fluid
+    p.u0 = np.zeros((n, 3))
+    p.u0[:, 2] = 0.02 + 0.002 * rng.uniform(-1, 1, n)
+    p.rho0 = 1 + 1e-3 * rng.uniform(-1, 1, n)
+    lat = H.make_lattice([p], "f32")
+    lat.autotune(16)
+    lat.step(24)
+    o = H.make_oracle(p)
+    o.step(24)
+    e = H.errors(lat.read_fields(0), o.read(), P0=p.P0)
+    record("tube32_full_size", e, dtype="f32", steps=24, launch=lat.info())
+    assert e["u"] <= 1e-5 and e["p"] <= 1e-5
+    lat.close()

@@ -1,0 +1,131 @@
+"""Host-side checks of the HIP library that need no GPU: it loads, exports
+every symbol the header declares, builds correct pull tables and boundary
+lists, and rejects invalid arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2108_08783_amd import inputs
+from paper_2108_08783_amd import lbm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+C = np.array([[0, 0, 0], [1, 0, 0], [-1, 0, 0], [0, 1, 0], [0, -1, 0], [0, 0, 1], [0, 0, -1],
+              [1, 1, 0], [-1, -1, 0], [1, -1, 0], [-1, 1, 0], [1, 0, 1], [-1, 0, -1],
+              [1, 0, -1], [-1, 0, 1], [0, 1, 1], [0, -1, -1], [0, 1, -1], [0, -1, 1]])
+BB, GHOST = np.iinfo(np.int32).min, np.iinfo(np.int32).min + 1
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    return sorted(set(re.findall(r"^(?:int|const char\*)\s+(lbm_\w+)\s*\(", text, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = lbm.load()
+    declared = header_functions()
+    assert declared == sorted(lbm.EXPORTS)
+    for name in declared:
+        assert hasattr(lib, name), name
+        assert ctypes.cast(getattr(lib, name), ctypes.c_void_p).value
+
+
+def test_cylinder_counts_match_independent_voxelisation():
+    # independent counts of the R=8, L=64 and R=32, L=512 tubes (site,
+    # boundary-site, wall-link and iolet-link numbers of the same shape).
+    for (R, L), want in {(8, 64): (12352, 3858, 17288, 1930),
+                         (32, 512): (1640960, 132890, 572936, 32050)}.items():
+        g = inputs.cylinder(R, L)
+        p = lbm.lbm_plan_export([g], wall_modes=[lbm.ELASTIC], tables=False)
+        assert (p["n_sites"], p["n_boundary"], p["n_wall_links"], p["n_iolet_links"]) == want
+
+
+def _index_grid(labels):
+    idx = -np.ones(labels.shape, np.int64)
+    fl = labels == 1
+    idx[fl] = np.arange(fl.sum())
+    return idx
+
+
+@pytest.mark.parametrize("mode", [lbm.BOUNCEBACK, lbm.ELASTIC])
+def test_pull_table_invariants(mode):
+    rng = np.random.default_rng(5)
+    geos = [inputs.separate_iolets(inputs.random_labels((7, 8, 9), rng)), inputs.cylinder(5, 9)]
+    p = lbm.lbm_plan_export(geos, wall_modes=[mode, mode])
+    nbr = p["nbr"]
+    N = p["n_sites"]
+    off = 0
+    reads = set()
+    bset = set(p["boundary"].tolist())
+    for g in geos:
+        lab = g.labels
+        idx = _index_grid(lab)
+        zz, yy, xx = np.nonzero(lab == 1)
+        for s, (z, y, x) in enumerate(zip(zz, yy, xx)):
+            gs = off + s
+            ghost = False
+            for i in range(1, 19):
+                sx, sy, sz = x - C[i, 0], y - C[i, 1], z - C[i, 2]
+                d = nbr[i - 1, gs]
+                srclab = lab[sz, sy, sx]
+                if srclab == 1:
+                    assert gs + d == off + idx[sz, sy, sx]
+                    reads.add((i, gs + d))
+                else:
+                    want = GHOST if (srclab >= 2 or mode == lbm.ELASTIC) else BB
+                    assert d == want
+                    ghost |= d == GHOST
+                    opp = i + 1 if i % 2 else i - 1
+                    reads.add((opp, gs))
+            assert (gs in bset) == ghost
+        off += g.n_fluid
+    # every slot (i >= 1) is read by exactly one site
+    assert len(reads) == 18 * N
+
+
+def test_boundary_masks_mark_every_non_bounce_back_link():
+    g = inputs.cylinder(4, 6)
+    p = lbm.lbm_plan_export([g], wall_modes=[lbm.ELASTIC])
+    for j, s in enumerate(p["boundary"]):
+        m = p["bmask"][j]
+        for i in range(1, 19):
+            assert bool(m >> i & 1) == (p["nbr"][i - 1, s] == GHOST)
+
+
+def test_sixteen_bit_offsets_fit_for_the_tube_workload():
+    p = lbm.lbm_plan_export([inputs.cylinder(32, 16)], tables=False)
+    # largest offset: one slice (3205 sites) plus about one row (2R)
+    assert 3205 < p["max_abs_offset"] < 3205 + 2 * 32 + 2
+
+
+@pytest.mark.parametrize("bad", ["border", "tau", "two_iolets", "dtype", "no_fluid"])
+def test_invalid_arguments_are_rejected_without_a_device(bad):
+    g = inputs.cylinder(3, 4)
+    tau, dtype = 0.8, "f32"
+    if bad == "border":
+        g.labels[2, 0, 3] = 1
+    elif bad == "tau":
+        tau = 0.5
+    elif bad == "two_iolets":
+        g = inputs.Geometry(labels=np.zeros((5, 5, 5), np.uint8))
+        g.labels[2, 2, 2] = 1
+        g.labels[2, 2, 1] = 2
+        g.labels[2, 2, 3] = 3
+    elif bad == "dtype":
+        dtype = 7
+    elif bad == "no_fluid":
+        g.labels[:] = 0
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_create_geometry([g], dtype, tau)
+    assert e.value.code == lbm.LBM_EINVAL
+    words = {"border": "border", "tau": "tau", "two_iolets": "iolets", "dtype": "dtype",
+             "no_fluid": "no fluid"}
+    assert words[bad] in str(e.value)
+
+
+def test_plan_rejects_zero_instances():
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_plan_export([], tables=False)
