@@ -1,0 +1,231 @@
+"""Throughput benchmark of the elastic-wall D3Q19 update on one MI355X.
+
+Workload (one step = one update of every fluid site, boundary pass included):
+elastic straight cylinder, radius 32, length 512 (1,640,960 fluid sites),
+D3Q19 BGK tau = 0.8, FP32 deviation storage, pulsatile parabolic velocity
+inlet u(t) = 0.02 (1 + 0.5 sin(2 pi t / 4000)), fixed-density outlet,
+stiffness k log-uniform in [1e-3, 1e-1] (seed 1), F = 0.85.
+
+Prints one JSON line: MLUPS (whole job), the HBM roofline of the update
+kernel (algorithmic bytes 2 * 19 * 4 per site per step over the kernel's
+average duration, measured with HIP events on the library's stream), and the
+FP64 CPU oracle timed on a bounded sample of the same workload.  Secondary
+figures (FP16/BF16 storage, bounce-back vs elastic) ride in "secondary".
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("MLUPS & % of HBM roofline (FP32 vs FP16 storage); cycles-to-periodic, warm vs cold")
+PEAK_GBS = 8000.0
+BYTES_PER_POP = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
+
+
+def tube_workload(R=32, L=512, seed=1):
+    import numpy as np
+    from paper_2108_08783_amd import inputs
+    g = inputs.cylinder(R, L)
+    rng = np.random.default_rng(seed)
+    k = float(inputs.log_uniform(rng, 1e-3, 1e-1))
+    return g, k
+
+
+def configure(obj, is_oracle, k, period=4000.0):
+    if is_oracle:
+        obj.set_wall(1, F=0.85, P0=1.0 / 3.0, k=[k])
+        obj.set_iolet(0, 1, 0.02, 0.5, period, 0.0, (0.0, 0.0, 1.0))
+        obj.set_iolet(1, 0, 1.0)
+        obj.init_fields()
+    else:
+        from paper_2108_08783_amd import lbm
+        obj.set_wall(0, lbm.ELASTIC, F=0.85, P0=1.0 / 3.0, k=[k])
+        obj.set_iolet(0, 0, lbm.VELOCITY, 0.02, 0.5, period, 0.0, (0.0, 0.0, 1.0))
+        obj.set_iolet(0, 1, lbm.DENSITY, 1.0)
+        obj.init_fields(0)
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "kernels.hpp", "d3q19.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2108_08783_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(dtype):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "update_kernel_tube32_traffic.json")
+    try:
+        d = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_hash") != kernel_hash():
+        return None
+    e = d.get("per_dtype", {}).get(dtype)
+    return None if e is None else e.get("bytes_per_launch")
+
+
+def copy_probe(gib=1.0, reps=20):
+    """Achievable HBM bandwidth of a plain device copy (torch) of known size;
+    under rocprofv3 --pmc it also gives the FETCH_SIZE / WRITE_SIZE scale."""
+    import torch
+    n = int(gib * (1 << 30)) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return dict(bytes_per_copy=2 * 4 * n, us=ms * 1e3, gbs=2 * 4 * n / (ms * 1e-3) / 1e9)
+
+
+def gpu_run(dtype, steps, warmup, mode="elastic", tune=True, launch=None):
+    import torch
+    from paper_2108_08783_amd import lbm
+    g, k = tube_workload()
+    lat = lbm.Lattice([g], dtype=dtype, tau=0.8)
+    configure(lat, False, k)
+    if mode == "bb":
+        lat.set_wall(0, lbm.BOUNCEBACK, F=0.0, P0=1.0 / 3.0, k=[k])
+    if launch:
+        lat.set_launch(**launch)
+    elif tune:
+        lat.autotune(128)
+    lat.step(warmup)
+    lat.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ms = lat.time_steps(steps)          # HIP events on the library stream
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    info = lat.info()
+    rho, u, _, _ = lat.read_fields(0, wss=False, wall_dr=False)  # raises if diverged
+    lat.close()
+    n = info["n_sites"]
+    return dict(n=n, wall_s=t1 - t0, event_ms=ms, info=info,
+                mlups=n * steps / (t1 - t0) / 1e6,
+                launch_us=ms * 1e3 / steps)
+
+
+def cpu_baseline(target_s=15.0):
+    """The FP64 oracle on the same tube, timed on this host's cores."""
+    import oracle
+    g, k = tube_workload()
+    o = oracle.Oracle(g.labels, 0.8, segment=g.segment, normal=g.normal,
+                      iolet_weight=g.iolet_weight)
+    configure(o, True, k)
+    o.step(2)
+    t0 = time.perf_counter()
+    o.step(3)
+    dt = (time.perf_counter() - t0) / 3
+    steps = max(3, int(target_s / max(dt, 1e-6)))
+    t0 = time.perf_counter()
+    o.step(steps)
+    el = time.perf_counter() - t0
+    return dict(value=o.n * steps / el / 1e6, unit="MLUPS", cores=oracle.num_threads(),
+                kind="oracle",
+                sample=f"{steps} steps of the same {o.n}-site elastic tube (FP64, OpenMP), "
+                       f"{el:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4000)
+    ap.add_argument("--warmup", type=int, default=256)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--dtype", default="f32")
+    ap.add_argument("--launch", default=None,
+                    help="JSON launch configuration instead of autotuning")
+    ap.add_argument("--probe-copy", action="store_true",
+                    help="only run the plain-copy bandwidth probe")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); "
+              "instances and domains would shard across GPUs as described in DESIGN.md",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+
+    if args.probe_copy:
+        print(json.dumps(dict(copy_probe=copy_probe())), flush=True)
+        return
+    launch = json.loads(args.launch) if args.launch else None
+    dtype = args.dtype
+    main_run = gpu_run(dtype, args.steps, args.warmup, launch=launch)
+    print(f"[bench] {dtype}: {main_run['mlups']:.0f} MLUPS, "
+          f"{main_run['launch_us']:.2f} us/step", file=sys.stderr, flush=True)
+    n = main_run["n"]
+    alg_bytes = 2 * 19 * BYTES_PER_POP[dtype] * n
+    achieved = alg_bytes / (main_run["launch_us"] * 1e-6) / 1e9
+    tr = traffic_from_profiles(dtype)
+    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / PEAK_GBS, 4), traffic=tr)
+
+    secondary = {}
+    if not args.no_secondary:
+        secondary["copy_probe"] = copy_probe()
+        for dt in ("f16", "bf16"):
+            r = gpu_run(dt, args.steps, args.warmup)
+            ach = 2 * 19 * BYTES_PER_POP[dt] * n / (r["launch_us"] * 1e-6) / 1e9
+            secondary[dt] = dict(mlups=round(r["mlups"], 1), us_per_step=round(r["launch_us"], 2),
+                                 roofline_frac=round(ach / PEAK_GBS, 4), achieved_gbs=round(ach, 1),
+                                 index_bits=r["info"]["index_bits"],
+                                 block=r["info"]["block_size"],
+                                 fused=r["info"]["boundary_fused"],
+                                 traffic=traffic_from_profiles(dt))
+            print(f"[bench] {dt}: {r['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+        bb = gpu_run(dtype, args.steps, args.warmup, mode="bb")
+        secondary["bounceback_" + dtype] = dict(
+            mlups=round(bb["mlups"], 1), us_per_step=round(bb["launch_us"], 2),
+            elastic_over_bb_time=round(main_run["launch_us"] / bb["launch_us"], 4))
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline()
+        print(f"[bench] oracle: {cpu['value']:.1f} MLUPS on {cpu['cores']} threads",
+              file=sys.stderr, flush=True)
+
+    info = main_run["info"]
+    out = dict(
+        metric=METRIC, value=round(main_run["mlups"], 1), unit="MLUPS", n_gpus=1,
+        steps=args.steps, warmup=args.warmup,
+        ms_per_step=round(main_run["wall_s"] * 1e3 / args.steps, 5),
+        higher_is_better=True, scaling="weak", vs_baseline=None, dtype=dtype,
+        data="synthetic",
+        config=dict(workload="elastic straight cylinder R=32 L=512, D3Q19 BGK tau=0.8, "
+                             "pulsatile parabolic velocity inlet 0.02(1+0.5 sin(2 pi t/4000)), "
+                             "density outlet, k log-uniform [1e-3,1e-1] seed 1, F=0.85",
+                    sites=n, boundary_sites=info["n_boundary"], storage=dtype,
+                    index_bits=info["index_bits"], block=info["block_size"],
+                    xcd_remap=info["xcd_remap"], nontemporal=info["nontemporal"],
+                    boundary_fused=info["boundary_fused"],
+                    graph_steps=128, parallelism="single GPU"),
+        roofline=roofline,
+        cpu_baseline=cpu,
+        secondary=secondary,
+        bytes_per_site=dict(algorithmic=2 * 19 * BYTES_PER_POP[dtype],
+                            model=round(info["bytes_per_site_model"], 2)),
+    )
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

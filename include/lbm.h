@@ -113,7 +113,7 @@ typedef struct {
     int32_t use_graph;       /* 1: lbm_step replays captured HIP graphs      */
     int32_t xcd_remap;       /* 1: block -> XCD-contiguous site ranges       */
     int32_t nontemporal;     /* 1: population stores bypass the caches       */
-    int32_t reserved;
+    int32_t boundary_fused;  /* 1: boundary links applied inside the update   */
     double bytes_per_site_algorithmic; /* 2 * 19 * sizeof(stored type)       */
     double bytes_per_site_model;       /* + neighbour table + boundary data  */
     int64_t device_bytes;    /* device memory held by the context            */
@@ -231,10 +231,14 @@ int lbm_instance_sites(const lbm_ctx* ctx, int inst, int64_t* n);
 
 /* Launch configuration of the update kernel.  block_size in {64, 128, 256,
  * 512, 1024}; index_bits 16 or 32 (16 only if every neighbour offset fits,
- * else LBM_EINVAL); use_graph, xcd_remap, nontemporal booleans.  A value of
- * -1 keeps the current setting. */
+ * else LBM_EINVAL); use_graph, xcd_remap, nontemporal booleans;
+ * boundary_fused 1: sites with elastic-wall or iolet links are updated by
+ * the same blocks as all other sites, which apply the link rules in place;
+ * 0: they are skipped there and updated by a compacted list of boundary
+ * sites in blocks appended to the same launch.  Both modes compute the same
+ * link rule.  A value of -1 keeps the current setting. */
 int lbm_set_launch(lbm_ctx* ctx, int block_size, int index_bits, int use_graph, int xcd_remap,
-                   int nontemporal);
+                   int nontemporal, int boundary_fused);
 
 /* Times every launch configuration on the context's own state for
  * steps_per_trial steps each (the populations are saved and restored), keeps

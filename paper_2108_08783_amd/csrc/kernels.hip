@@ -186,62 +186,24 @@ __device__ __forceinline__ int remap_xcd(int b, int nblk) {
     return j * per + (j < rem ? j : rem) + k;
 }
 
-template <int DT, typename I>
-__device__ __forceinline__ void interior_site(const StepArgs& a, int x) {
-    using raw = typename Codec<DT>::raw;
-    using acc = typename Codec<DT>::acc;
-    const raw* __restrict__ A = (const raw*)a.A;
-    raw* __restrict__ B = (raw*)a.B;
-    I d[18];
-    load_offsets<I>((const I*)a.nbr, a.np, x, d);
-    bool ghost = false;
-#pragma unroll
-    for (int i = 0; i < 18; ++i) ghost |= (d[i] == Sentinel<I>::GHOST);
-    if (ghost) return;  // updated by the boundary pass
-    acc h[Q];
-    gather<DT, I>(A, a.np, x, d, h);
-    const Mom<acc> m = moments(h);
-    acc e[Q];
-    heq(m.drho, m.rho, m.ux, m.uy, m.uz, e);
-    const acc om = (acc)a.omega;
-    const bool nt = a.nontemporal != 0;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) put(B + (int64_t)i * a.np + x, Codec<DT>::enc(h[i] + om * (e[i] - h[i])), nt);
-}
-
-// Boundary site: the same pull and BGK collision, then for every link i whose
-// upstream voxel is an elastic wall or an iolet the value
+// Links whose upstream voxel is an elastic wall or an iolet (boundary record
+// j of a site with moments m, equilibrium deviations e and post-collision
+// deviations hs): for each such link i the value
 //   f_i(x, t+1) = feq_i(rho', U') + (1 - 1/tau) (f_i - feq_i(rho, u))
 //              = feq_i(rho', U') + f*_i - feq_i(rho, u)
-// is written into slot (opp(i), x), which the site pulls at the next step.
+// replaces out[opp(i)], the slot the site pulls for link i at the next step.
 //   elastic wall (Sec. 2.3): rho' = rho, U' = s u,
 //     s = (F + Delta r - 1) / Delta r, Delta r = 1 + Delta E,
 //     Delta E = max(0, (p - P0) / k), p = rho / 3;
 //   density iolet (Sec. 3): rho' = rho_io(t), U' = u;
 //   velocity iolet (Sec. 3): rho' = rho, U' = weight(x) u_io(t) dir.
-template <int DT, typename I>
-__device__ __forceinline__ void boundary_site(const StepArgs& a, int j) {
-    using raw = typename Codec<DT>::raw;
-    using acc = typename Codec<DT>::acc;
-    const raw* __restrict__ A = (const raw*)a.A;
-    raw* __restrict__ B = (raw*)a.B;
-    const int x = a.bsite[j];
-    I d[18];
-    load_offsets<I>((const I*)a.nbr, a.np, x, d);
-    acc h[Q];
-    gather<DT, I>(A, a.np, x, d, h);
-    const Mom<acc> m = moments(h);
-    acc e[Q];
-    heq(m.drho, m.rho, m.ux, m.uy, m.uz, e);
-    const acc om = (acc)a.omega;
-    acc hs[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) hs[i] = h[i] + om * (e[i] - h[i]);
-
+template <typename acc>
+__device__ __forceinline__ void apply_links(const StepArgs& a, int j, const Mom<acc>& m,
+                                            const acc (&e)[Q], const acc (&hs)[Q],
+                                            acc (&out)[Q]) {
     const uint32_t bw = a.bwall[j], bi = a.bio[j];
     const uint32_t wmask = bw & 0x7FFFEu, imask = bi & 0x7FFFEu;
     const uint32_t inst = bw >> 19;
-    // elastic wall: slip factor s
     acc s = 0;
     if (wmask) {
         const InstParams& P = a.ip[inst];
@@ -250,7 +212,6 @@ __device__ __forceinline__ void boundary_site(const StepArgs& a, int j) {
         s = ((acc)P.F + dE) / ((acc)1 + dE);
     }
     const acc wx = s * m.ux, wy = s * m.uy, wz = s * m.uz;
-    // iolet: prescribed density or velocity
     acc idr = m.drho, ir = m.rho, ix = m.ux, iy = m.uy, iz = m.uz;
     if (imask) {
         const IoletParams& q = a.iop[bi >> 19];
@@ -267,9 +228,6 @@ __device__ __forceinline__ void boundary_site(const StepArgs& a, int j) {
             iz = sp * (acc)q.dir[2];
         }
     }
-    acc out[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) out[i] = hs[i];
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
         const bool isw = (wmask >> i) & 1u, isi = (imask >> i) & 1u;
@@ -278,6 +236,39 @@ __device__ __forceinline__ void boundary_site(const StepArgs& a, int j) {
             const acc px = isi ? ix : wx, py = isi ? iy : wy, pz = isi ? iz : wz;
             out[dopp(i)] = heq_one<acc>(i, pdr, pr, px, py, pz) + hs[i] - e[i];
         }
+    }
+}
+
+// One site: pull, BGK collision (Sec. 2.1 eq. LBE_SRT) and store.  A site
+// with boundary-pass links either returns (compacted mode: the boundary
+// blocks update it) or applies the link rules in place (fused mode), using
+// its boundary record from bidx.
+template <int DT, typename I>
+__device__ __forceinline__ void update_site(const StepArgs& a, int x, int j_compact) {
+    using raw = typename Codec<DT>::raw;
+    using acc = typename Codec<DT>::acc;
+    const raw* __restrict__ A = (const raw*)a.A;
+    raw* __restrict__ B = (raw*)a.B;
+    I d[18];
+    load_offsets<I>((const I*)a.nbr, a.np, x, d);
+    bool ghost = false;
+#pragma unroll
+    for (int i = 0; i < 18; ++i) ghost |= (d[i] == Sentinel<I>::GHOST);
+    if (ghost && j_compact < 0 && !a.fused) return;  // updated by the boundary blocks
+    acc h[Q];
+    gather<DT, I>(A, a.np, x, d, h);
+    const Mom<acc> m = moments(h);
+    acc e[Q];
+    heq(m.drho, m.rho, m.ux, m.uy, m.uz, e);
+    const acc om = (acc)a.omega;
+    acc out[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) out[i] = h[i] + om * (e[i] - h[i]);
+    if (ghost) {
+        const acc hs[Q] = {out[0], out[1], out[2], out[3], out[4], out[5], out[6],
+                           out[7], out[8], out[9], out[10], out[11], out[12],
+                           out[13], out[14], out[15], out[16], out[17], out[18]};
+        apply_links<acc>(a, j_compact >= 0 ? j_compact : a.bidx[x], m, e, hs, out);
     }
     const bool nt = a.nontemporal != 0;
 #pragma unroll
@@ -290,10 +281,10 @@ __global__ __launch_bounds__(1024) void k_step(StepArgs a) {
     if (b < a.n_int_blocks) {
         const int lb = a.xcd_remap ? remap_xcd(b, a.n_int_blocks) : b;
         const int x = lb * (int)blockDim.x + (int)threadIdx.x;
-        if (x < a.n) interior_site<DT, I>(a, x);
+        if (x < a.n) update_site<DT, I>(a, x, -1);
     } else {
         const int j = (b - a.n_int_blocks) * (int)blockDim.x + (int)threadIdx.x;
-        if (j < a.nb) boundary_site<DT, I>(a, j);
+        if (j < a.nb) update_site<DT, I>(a, a.bsite[j], j);
     }
     if (b == 0 && threadIdx.x == 0) a.clock[a.clock_in ^ 1] = a.clock[a.clock_in] + 1;
 }
@@ -493,7 +484,7 @@ hipError_t dispatch(int dtype, int ibits, Args&&... args) {
 template <int DT, typename I>
 struct StepL {
     static hipError_t run(const StepArgs& a, int block, hipStream_t s) {
-        const int nblk = a.n_int_blocks + cdiv(a.nb, block);
+        const int nblk = a.n_int_blocks + (a.fused ? 0 : cdiv(a.nb, block));
         hipLaunchKernelGGL((k_step<DT, I>), dim3(nblk), dim3(block), 0, s, a);
         return hipGetLastError();
     }

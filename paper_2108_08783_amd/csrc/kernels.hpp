@@ -36,8 +36,11 @@ struct StepArgs {
     int32_t xcd_remap;
     int32_t nontemporal;
     int32_t clock_in;       // clock slot read this step; the other is written
+    int32_t fused;          // 1: boundary links applied inside the update blocks
+    int32_t pad;
     double omega;           // 1 / tau
     const int32_t* bsite;
+    const int32_t* bidx;    // per site: boundary record index (fused mode)
     const uint32_t* bwall;  // elastic wall link mask | inst << 19
     const uint32_t* bio;    // iolet link mask | iolet slot << 19
     const int32_t* bk;      // stiffness index

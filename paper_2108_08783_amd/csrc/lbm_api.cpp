@@ -48,7 +48,7 @@ struct TuneKey {
     }
 };
 struct TuneVal {
-    int block, ibits, xcd, nt;
+    int block, ibits, xcd, nt, fused;
 };
 std::mutex g_tune_mu;
 std::map<TuneKey, TuneVal> g_tune_cache;
@@ -74,6 +74,7 @@ struct lbm_ctx {
     void* nbr16 = nullptr;
     bool have16 = false;
     int32_t* bsite = nullptr;
+    int32_t* bidx = nullptr;   // per site: boundary record index, -1 if none
     uint32_t* bwall = nullptr;
     uint32_t* bio = nullptr;
     int32_t* bk = nullptr;
@@ -92,7 +93,7 @@ struct lbm_ctx {
     int64_t step = 0;
     bool tables_dirty = true, params_dirty = true;
     // launch configuration
-    int block = 256, ibits = 32, use_graph = 1, xcd = 1, nt = 0;
+    int block = 256, ibits = 32, use_graph = 1, xcd = 1, nt = 0, fused = 1;
     hipStream_t stream = nullptr;
     hipGraphExec_t graph[2] = {nullptr, nullptr};  // by buffer parity at start
     int64_t device_bytes = 0;
@@ -214,6 +215,12 @@ int sync_tables(lbm_ctx* c) {
     rc = rc ? rc : upload(c, c->bk, bl.kidx.data(), nb * 4);
     rc = rc ? rc : upload(c, c->bw, bl.weight.data(), nb * 4);
     if (rc) return rc;
+    {
+        std::vector<int32_t> bidx(c->plan.N, -1);
+        for (int64_t j = 0; j < nb; ++j) bidx[bl.site[j]] = (int32_t)j;
+        rc = upload(c, c->bidx, bidx.data(), bidx.size() * 4);
+        if (rc) return rc;
+    }
     c->tables_dirty = false;
     drop_graphs(c);
     return LBM_OK;
@@ -269,8 +276,11 @@ StepArgs step_args(const lbm_ctx* c, int parity) {
     a.xcd_remap = c->xcd;
     a.nontemporal = c->nt;
     a.clock_in = parity;
+    a.fused = c->fused;
+    a.pad = 0;
     a.omega = 1.0 / c->tau;
     a.bsite = c->bsite;
+    a.bidx = c->bidx;
     a.bwall = c->bwall;
     a.bio = c->bio;
     a.bk = c->bk;
@@ -480,6 +490,7 @@ int lbm_create_geometry(lbm_ctx** out, const lbm_instance_desc* inst, int n_inst
     rc = rc ? rc : dalloc(c, &c->buf[0], pop_bytes);
     rc = rc ? rc : dalloc(c, &c->buf[1], pop_bytes);
     rc = rc ? rc : dalloc(c, &c->nbr32, (size_t)18 * c->np * 4);
+    rc = rc ? rc : dalloc(c, (void**)&c->bidx, (size_t)c->plan.N * 4);
     if (c->have16) rc = rc ? rc : dalloc(c, &c->nbr16, (size_t)18 * c->np * 2);
     const int64_t nw = (int64_t)c->plan.wall_site.size();
     rc = rc ? rc : dalloc(c, (void**)&c->wsite, nw * 4);
@@ -792,6 +803,7 @@ int lbm_get_info(const lbm_ctx* c, lbm_info* info) {
     info->use_graph = c->use_graph;
     info->xcd_remap = c->xcd;
     info->nontemporal = c->nt;
+    info->boundary_fused = c->fused;
     info->bytes_per_site_algorithmic = 2.0 * Q * (double)c->esize;
     const double N = (double)std::max<int64_t>(1, c->plan.N);
     info->bytes_per_site_model = 2.0 * Q * (double)c->esize + 18.0 * (c->ibits / 8) +
@@ -808,7 +820,7 @@ int lbm_instance_sites(const lbm_ctx* c, int inst, int64_t* n) {
 }
 
 int lbm_set_launch(lbm_ctx* c, int block_size, int index_bits, int use_graph, int xcd_remap,
-                   int nontemporal) {
+                   int nontemporal, int boundary_fused) {
     if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
     if (block_size != -1 && block_size != 64 && block_size != 128 && block_size != 256 &&
         block_size != 512 && block_size != 1024)
@@ -823,6 +835,7 @@ int lbm_set_launch(lbm_ctx* c, int block_size, int index_bits, int use_graph, in
     if (use_graph != -1) c->use_graph = use_graph ? 1 : 0;
     if (xcd_remap != -1) c->xcd = xcd_remap ? 1 : 0;
     if (nontemporal != -1) c->nt = nontemporal ? 1 : 0;
+    if (boundary_fused != -1) c->fused = boundary_fused ? 1 : 0;
     drop_graphs(c);
     return LBM_OK;
 }
@@ -838,7 +851,7 @@ int lbm_autotune(lbm_ctx* c, int steps_per_trial, double* best_rate) {
         auto it = g_tune_cache.find(key);
         if (it != g_tune_cache.end() && !best_rate) {
             const TuneVal& v = it->second;
-            return lbm_set_launch(c, v.block, v.ibits, -1, v.xcd, v.nt);
+            return lbm_set_launch(c, v.block, v.ibits, -1, v.xcd, v.nt, v.fused);
         }
     }
     // save the state: both buffers and the clock
@@ -854,17 +867,19 @@ int lbm_autotune(lbm_ctx* c, int steps_per_trial, double* best_rate) {
     HIP_TRY(c, hipMemcpyAsync(clock_save, c->clock, sizeof(clock_save), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     const int64_t step_save = c->step;
-    const int old_block = c->block, old_ibits = c->ibits, old_xcd = c->xcd, old_nt = c->nt;
-    TuneVal best{old_block, old_ibits, old_xcd, old_nt};
+    const int old_block = c->block, old_ibits = c->ibits, old_xcd = c->xcd, old_nt = c->nt,
+              old_fused = c->fused;
+    TuneVal best{old_block, old_ibits, old_xcd, old_nt, old_fused};
     double best_ms = std::numeric_limits<double>::infinity();
     const int blocks[] = {128, 256, 512, 1024};
     const int ibits_list[] = {16, 32};
     for (int ib : ibits_list) {
         if (ib == 16 && !c->have16) continue;
+        for (int fu = 0; fu < 2 && !rc; ++fu)
         for (int bs : blocks)
             for (int xr = 0; xr < 2; ++xr)
                 for (int ntv = 0; ntv < 2; ++ntv) {
-                    rc = lbm_set_launch(c, bs, ib, -1, xr, ntv);
+                    rc = lbm_set_launch(c, bs, ib, -1, xr, ntv, fu);
                     if (rc) break;
                     double ms = 0;
                     rc = run_steps(c, 2);  // warm-up (and graph build)
@@ -872,7 +887,7 @@ int lbm_autotune(lbm_ctx* c, int steps_per_trial, double* best_rate) {
                     if (rc) break;
                     if (ms < best_ms) {
                         best_ms = ms;
-                        best = {bs, ib, xr, ntv};
+                        best = {bs, ib, xr, ntv, fu};
                     }
                 }
         if (rc) break;
@@ -886,10 +901,10 @@ int lbm_autotune(lbm_ctx* c, int steps_per_trial, double* best_rate) {
     dfree(c, save1);
     c->step = step_save;
     if (rc) {
-        lbm_set_launch(c, old_block, old_ibits, -1, old_xcd, old_nt);
+        lbm_set_launch(c, old_block, old_ibits, -1, old_xcd, old_nt, old_fused);
         return rc;
     }
-    rc = lbm_set_launch(c, best.block, best.ibits, -1, best.xcd, best.nt);
+    rc = lbm_set_launch(c, best.block, best.ibits, -1, best.xcd, best.nt, best.fused);
     if (rc) return rc;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);

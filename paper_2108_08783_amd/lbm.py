@@ -57,12 +57,12 @@ class Info(ctypes.Structure):
                 ("n_instances", ctypes.c_int32), ("dtype", ctypes.c_int32),
                 ("index_bits", ctypes.c_int32), ("block_size", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
-                ("nontemporal", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("nontemporal", ctypes.c_int32), ("boundary_fused", ctypes.c_int32),
                 ("bytes_per_site_algorithmic", ctypes.c_double),
                 ("bytes_per_site_model", ctypes.c_double), ("device_bytes", ctypes.c_int64)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 _lib = None
@@ -95,7 +95,7 @@ def load():
         "lbm_cycle_delta": [P, I, P, P],
         "lbm_get_info": [P, P],
         "lbm_instance_sites": [P, I, P],
-        "lbm_set_launch": [P, I, I, I, I, I],
+        "lbm_set_launch": [P, I, I, I, I, I, I],
         "lbm_autotune": [P, I, P],
         "lbm_plan_export": [P, I, P, P, P, P, P],
     }
@@ -233,9 +233,9 @@ def lbm_get_info(ctx):
 
 
 def lbm_set_launch(ctx, block_size=-1, index_bits=-1, use_graph=-1, xcd_remap=-1,
-                   nontemporal=-1):
-    _check(load().lbm_set_launch(ctx, block_size, index_bits, use_graph, xcd_remap, nontemporal),
-           ctx)
+                   nontemporal=-1, boundary_fused=-1):
+    _check(load().lbm_set_launch(ctx, block_size, index_bits, use_graph, xcd_remap, nontemporal,
+                                 boundary_fused), ctx)
 
 
 def lbm_autotune(ctx, steps_per_trial=64):

@@ -62,14 +62,17 @@ def test_small_tube_density_driven(dtype, mode):
         assert e["dr"] <= 1e-6
 
 
+@pytest.mark.parametrize("fused", [1, 0])
 @pytest.mark.parametrize("dtype", ["f64", "f32", "f16", "bf16"])
-def test_pulsatile_elastic_tube(dtype):
+def test_pulsatile_elastic_tube(dtype, fused):
     """R=12, L=96 elastic tube with a pulsatile parabolic velocity inlet
-    (u0 = 0.02, amplitude 0.5) and a density outlet, 1000 steps."""
+    (u0 = 0.02, amplitude 0.5) and a density outlet, 1000 steps, with the
+    boundary links applied in the update blocks (fused) or by the compacted
+    boundary blocks."""
     p = H.tube_problem(12, 96, seed=1)
-    g, r = run_pair(p, dtype, 1000)
+    g, r = run_pair(p, dtype, 1000, launch=dict(boundary_fused=fused))
     e = H.errors(g, r, P0=p.P0)
-    record("tube12_pulsatile_elastic", e, dtype=dtype, steps=1000)
+    record("tube12_pulsatile_elastic", e, dtype=dtype, steps=1000, fused=fused)
     if dtype in TOL:
         assert e["u"] <= TOL[dtype] and e["p"] <= TOL[dtype]
         assert e["wss"] <= 10 * TOL[dtype]
@@ -78,15 +81,16 @@ def test_pulsatile_elastic_tube(dtype):
         assert e["u"] <= bound and e["p"] <= bound
 
 
+@pytest.mark.parametrize("fused", [1, 0])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("seed", [1, 2])
-def test_random_boxes_every_link_type(dtype, seed):
+def test_random_boxes_every_link_type(dtype, seed, fused):
     """Random labels (walls, two iolets, thin gaps, opposite wall pairs),
     three stiffness segments, random initial state, 60 steps."""
     p = H.random_box_problem(seed)
-    g, r = run_pair(p, dtype, 60)
+    g, r = run_pair(p, dtype, 60, launch=dict(boundary_fused=fused))
     e = H.errors(g, r, P0=p.P0)
-    record(f"random_box_{seed}", e, dtype=dtype, steps=60)
+    record(f"random_box_{seed}", e, dtype=dtype, steps=60, fused=fused)
     tol = TOL[dtype]
     assert e["u"] <= 10 * tol and e["p"] <= tol and e["wss"] <= 100 * tol
 
@@ -134,7 +138,8 @@ def test_single_site_instances():
     del rng
 
 
-def test_launch_configurations_are_bit_identical():
+@pytest.mark.parametrize("fused", [1, 0])
+def test_launch_configurations_are_bit_identical(fused):
     """Block size, index width, graph replay, XCD remapping and non-temporal
     stores change only the schedule, never the arithmetic."""
     p = H.tube_problem(10, 40, seed=6)
@@ -144,7 +149,7 @@ def test_launch_configurations_are_bit_identical():
                 dict(block_size=1024, index_bits=16, use_graph=1, xcd_remap=0, nontemporal=0),
                 dict(block_size=512, index_bits=32, use_graph=1, xcd_remap=1, nontemporal=1)]:
         lat = H.make_lattice([p], "f32")
-        lat.set_launch(**cfg)
+        lat.set_launch(boundary_fused=fused, **cfg)
         lat.step(300)
         f = lat.read_populations(0)
         lat.close()
