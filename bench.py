@@ -29,27 +29,13 @@ PEAK_GBS = 8000.0
 BYTES_PER_POP = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
 
 
-def tube_workload(R=32, L=512, seed=1):
-    import numpy as np
-    from paper_2108_08783_amd import inputs
-    g = inputs.cylinder(R, L)
-    rng = np.random.default_rng(seed)
-    k = float(inputs.log_uniform(rng, 1e-3, 1e-1))
-    return g, k
-
-
-def configure(obj, is_oracle, k, period=4000.0):
-    if is_oracle:
-        obj.set_wall(1, F=0.85, P0=1.0 / 3.0, k=[k])
-        obj.set_iolet(0, 1, 0.02, 0.5, period, 0.0, (0.0, 0.0, 1.0))
-        obj.set_iolet(1, 0, 1.0)
-        obj.init_fields()
-    else:
-        from paper_2108_08783_amd import lbm
-        obj.set_wall(0, lbm.ELASTIC, F=0.85, P0=1.0 / 3.0, k=[k])
-        obj.set_iolet(0, 0, lbm.VELOCITY, 0.02, 0.5, period, 0.0, (0.0, 0.0, 1.0))
-        obj.set_iolet(0, 1, lbm.DENSITY, 1.0)
-        obj.init_fields(0)
+def oracle_configure(o, wl, k=0):
+    p = wl.params[k]
+    o.set_wall(p.mode, F=p.F, P0=p.P0, k=p.k)
+    for i, q in p.iolets.items():
+        o.set_iolet(i, q["kind"], q["a0"], q.get("amp", 0.0), q.get("period", 1.0),
+                    q.get("phase", 0.0), q.get("direction", (0.0, 0.0, 0.0)))
+    o.init_fields()
 
 
 def kernel_hash():
@@ -93,14 +79,13 @@ def copy_probe(gib=1.0, reps=20):
     return dict(bytes_per_copy=2 * 4 * n, us=ms * 1e3, gbs=2 * 4 * n / (ms * 1e-3) / 1e9)
 
 
-def gpu_run(dtype, steps, warmup, mode="elastic", tune=True, launch=None):
+def gpu_run(wl, dtype, steps, warmup, bounceback=False, tune=True, launch=None):
     import torch
-    from paper_2108_08783_amd import lbm
-    g, k = tube_workload()
-    lat = lbm.Lattice([g], dtype=dtype, tau=0.8)
-    configure(lat, False, k)
-    if mode == "bb":
-        lat.set_wall(0, lbm.BOUNCEBACK, F=0.0, P0=1.0 / 3.0, k=[k])
+    from paper_2108_08783_amd import lbm, workloads
+    lat = workloads.lattice(wl, dtype)
+    if bounceback:
+        for k, p in enumerate(wl.params):
+            lat.set_wall(k, lbm.BOUNCEBACK, F=0.0, P0=p.P0, k=p.k)
     if launch:
         lat.set_launch(**launch)
     elif tune:
@@ -113,7 +98,8 @@ def gpu_run(dtype, steps, warmup, mode="elastic", tune=True, launch=None):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     info = lat.info()
-    rho, u, _, _ = lat.read_fields(0, wss=False, wall_dr=False)  # raises if diverged
+    for k in range(len(wl.geoms)):
+        lat.read_fields(k, wss=False, wall_dr=False)  # raises if diverged
     lat.close()
     n = info["n_sites"]
     return dict(n=n, wall_s=t1 - t0, event_ms=ms, info=info,
@@ -121,13 +107,24 @@ def gpu_run(dtype, steps, warmup, mode="elastic", tune=True, launch=None):
                 launch_us=ms * 1e3 / steps)
 
 
-def cpu_baseline(target_s=15.0):
+def summary(r, dtype, with_traffic=False):
+    ach = 2 * 19 * BYTES_PER_POP[dtype] * r["n"] / (r["launch_us"] * 1e-6) / 1e9
+    out = dict(sites=r["n"], mlups=round(r["mlups"], 1), us_per_step=round(r["launch_us"], 2),
+               roofline_frac=round(ach / PEAK_GBS, 4), achieved_gbs=round(ach, 1),
+               index_bits=r["info"]["index_bits"], block=r["info"]["block_size"],
+               fused=r["info"]["boundary_fused"], boundary_sites=r["info"]["n_boundary"])
+    if with_traffic:
+        out["traffic"] = traffic_from_profiles(dtype)
+    return out
+
+
+def cpu_baseline(wl, target_s=15.0):
     """The FP64 oracle on the same tube, timed on this host's cores."""
     import oracle
-    g, k = tube_workload()
-    o = oracle.Oracle(g.labels, 0.8, segment=g.segment, normal=g.normal,
+    g = wl.geoms[0]
+    o = oracle.Oracle(g.labels, wl.tau, segment=g.segment, normal=g.normal,
                       iolet_weight=g.iolet_weight)
-    configure(o, True, k)
+    oracle_configure(o, wl)
     o.step(2)
     t0 = time.perf_counter()
     o.step(3)
@@ -167,10 +164,12 @@ def main():
     if args.probe_copy:
         print(json.dumps(dict(copy_probe=copy_probe())), flush=True)
         return
+    from paper_2108_08783_amd import workloads
     launch = json.loads(args.launch) if args.launch else None
     dtype = args.dtype
-    main_run = gpu_run(dtype, args.steps, args.warmup, launch=launch)
-    print(f"[bench] {dtype}: {main_run['mlups']:.0f} MLUPS, "
+    tube = workloads.tube32()
+    main_run = gpu_run(tube, dtype, args.steps, args.warmup, launch=launch)
+    print(f"[bench] tube {dtype}: {main_run['mlups']:.0f} MLUPS, "
           f"{main_run['launch_us']:.2f} us/step", file=sys.stderr, flush=True)
     n = main_run["n"]
     alg_bytes = 2 * 19 * BYTES_PER_POP[dtype] * n
@@ -183,23 +182,28 @@ def main():
     if not args.no_secondary:
         secondary["copy_probe"] = copy_probe()
         for dt in ("f16", "bf16"):
-            r = gpu_run(dt, args.steps, args.warmup)
-            ach = 2 * 19 * BYTES_PER_POP[dt] * n / (r["launch_us"] * 1e-6) / 1e9
-            secondary[dt] = dict(mlups=round(r["mlups"], 1), us_per_step=round(r["launch_us"], 2),
-                                 roofline_frac=round(ach / PEAK_GBS, 4), achieved_gbs=round(ach, 1),
-                                 index_bits=r["info"]["index_bits"],
-                                 block=r["info"]["block_size"],
-                                 fused=r["info"]["boundary_fused"],
-                                 traffic=traffic_from_profiles(dt))
-            print(f"[bench] {dt}: {r['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
-        bb = gpu_run(dtype, args.steps, args.warmup, mode="bb")
-        secondary["bounceback_" + dtype] = dict(
-            mlups=round(bb["mlups"], 1), us_per_step=round(bb["launch_us"], 2),
-            elastic_over_bb_time=round(main_run["launch_us"] / bb["launch_us"], 4))
+            r = gpu_run(tube, dt, args.steps, args.warmup)
+            secondary["tube_" + dt] = summary(r, dt, with_traffic=True)
+            print(f"[bench] tube {dt}: {r['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+        bb = gpu_run(tube, dtype, args.steps, args.warmup, bounceback=True)
+        secondary["tube_bounceback_" + dtype] = dict(
+            summary(bb, dtype), elastic_over_bb_time=round(main_run["launch_us"] / bb["launch_us"], 4))
+        tree = workloads.tree()
+        for dt in ("f32", "f16", "bf16"):
+            r = gpu_run(tree, dt, args.steps // 4, args.warmup)
+            secondary["tree_" + dt] = summary(r, dt)
+            print(f"[bench] tree {dt}: {r['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+        del tree
+        sw = workloads.sweep()
+        for dt in ("f16", "f32"):
+            r = gpu_run(sw, dt, args.steps // 8, args.warmup // 4)
+            secondary["sweep64_" + dt] = summary(r, dt)
+            print(f"[bench] sweep {dt}: {r['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+        del sw
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline()
+        cpu = cpu_baseline(tube)
         print(f"[bench] oracle: {cpu['value']:.1f} MLUPS on {cpu['cores']} threads",
               file=sys.stderr, flush=True)
 

@@ -169,3 +169,286 @@ def density_perturbation(n: int, seed: int, amplitude: float = 1e-6) -> np.ndarr
 
 def log_uniform(rng: np.random.Generator, lo: float, hi: float, size=None):
     return np.exp(rng.uniform(math.log(lo), math.log(hi), size=size))
+
+
+# ------------------------------------------------------ branching vessels --
+@dataclasses.dataclass
+class Segment:
+    p0: np.ndarray          # start point (x, y, z) in voxel units
+    p1: np.ndarray          # end point
+    r0: float               # radius at p0
+    r1: float               # radius at p1
+    gen: int = 0            # generation (root 0)
+    outlet: bool = False    # flat end with an outlet cap
+    inlet: bool = False     # flat start on the inlet plane
+    sid: int = 0
+
+
+def _rot(v, axis, ang):
+    """Rotate v about unit axis by ang (Rodrigues)."""
+    axis = axis / np.linalg.norm(axis)
+    return (v * math.cos(ang) + np.cross(axis, v) * math.sin(ang)
+            + axis * np.dot(axis, v) * (1 - math.cos(ang)))
+
+
+def _perp(d):
+    a = np.array([0.0, 0.0, 1.0]) if abs(d[2]) < 0.9 else np.array([0.0, 1.0, 0.0])
+    p = np.cross(d, a)
+    return p / np.linalg.norm(p)
+
+
+def voxelise(segments: List[Segment], shape, iolet_of_segment=None) -> Geometry:
+    """Union of tapered round-ended tubes.  Outlet segments end flat at p1
+    with an outlet cap (one voxel layer beyond the end plane); the inlet
+    segment starts flat on the inlet plane x = 0.  Segment id = first
+    segment containing the voxel.  Inlet weights are parabolic in the
+    distance from the inlet segment's axis."""
+    nz, ny, nx = shape
+    lab = np.zeros(shape, np.uint8)
+    seg = np.zeros(shape, np.uint16)
+    claimed = np.zeros(shape, bool)
+    iw = np.zeros(shape, np.float32)
+    iolets = []
+    next_io = 1  # 0 is the inlet
+
+    def bbox(pts, pad):
+        lo = np.floor(np.min(pts, 0) - pad).astype(int)
+        hi = np.ceil(np.max(pts, 0) + pad).astype(int) + 1
+        lo = np.maximum(lo, 0)
+        hi = np.minimum(hi, [nx, ny, nz])
+        return lo, hi
+
+    def local(s, lo, hi):
+        z, y, x = np.ogrid[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]]
+        d = s.p1 - s.p0
+        dd = float(d @ d)
+        rx, ry, rz = x - s.p0[0], y - s.p0[1], z - s.p0[2]
+        t = (rx * d[0] + ry * d[1] + rz * d[2]) / dd
+        return rx, ry, rz, t, d, dd
+
+    # outlet caps first (fluid overrides them)
+    for s in segments:
+        if not s.outlet:
+            continue
+        io = next_io
+        next_io += 1
+        lo, hi = bbox([s.p1], s.r1 + 3)
+        rx, ry, rz, t, d, dd = local(s, lo, hi)
+        L = math.sqrt(dd)
+        ax = t * L
+        px, py, pz = rx - t * d[0], ry - t * d[1], rz - t * d[2]
+        rad2 = px * px + py * py + pz * pz
+        cap = (ax > L) & (ax <= L + 1.8) & (rad2 < (s.r1 + 1.8) ** 2)
+        sub = lab[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]]
+        sub[cap] = IOLET0 + io
+        iolets.append(dict(id=io, role="outlet", direction=tuple(-d / L), segment=s.sid))
+    for s in segments:
+        r_max = max(s.r0, s.r1)
+        lo, hi = bbox([s.p0, s.p1], r_max + 2)
+        rx, ry, rz, t, d, dd = local(s, lo, hi)
+        tc = np.clip(t, 0.0, 1.0)
+        px, py, pz = rx - tc * d[0], ry - tc * d[1], rz - tc * d[2]
+        rad2 = px * px + py * py + pz * pz
+        r = s.r0 + tc * (s.r1 - s.r0)
+        inside = rad2 < r * r
+        if s.outlet:
+            inside &= t <= 1.0
+        z0, y0, x0 = lo[2], lo[1], lo[0]
+        sl = (slice(z0, hi[2]), slice(y0, hi[1]), slice(x0, hi[0]))
+        if s.inlet:
+            xs = np.arange(lo[0], hi[0])[None, None, :]
+            inside &= xs >= 1
+            w = np.where(inside, 2.0 * (1.0 - rad2 / (s.r0 * s.r0)), 0.0)
+            iw[sl] = np.maximum(iw[sl], np.clip(w, 0.0, None).astype(np.float32))
+        new = inside & ~claimed[sl]
+        seg[sl][new] = s.sid
+        claimed[sl] |= inside
+        lab[sl][inside] = FLUID
+    # inlet plane x = 0 (around the inlet segment)
+    for s in segments:
+        if s.inlet:
+            lo, hi = bbox([s.p0], s.r0 + 3)
+            y, z = np.ogrid[lo[1]:hi[1], lo[2]:hi[2]]
+            disk = (y - s.p0[1]) ** 2 + (z - s.p0[2]) ** 2 < (s.r0 + 1.8) ** 2
+            plane = lab[lo[2]:hi[2], lo[1]:hi[1], 0]
+            plane[disk.T] = IOLET0 + 0
+            iolets.insert(0, dict(id=0, role="inlet", direction=tuple((s.p1 - s.p0) /
+                                                                      np.linalg.norm(s.p1 - s.p0))))
+    _resolve_iolet_conflicts(lab)
+    g = Geometry(labels=lab, segment=seg, iolet_weight=iw, n_seg=len(segments))
+    g.iolets = iolets
+    return g
+
+
+_OFFS18 = [(dx, dy, dz) for dx in (-1, 0, 1) for dy in (-1, 0, 1) for dz in (-1, 0, 1)
+           if 0 < dx * dx + dy * dy + dz * dz <= 2]
+
+
+def _resolve_iolet_conflicts(lab):
+    """Vectorised form of separate_iolets: a fluid voxel whose upstream
+    neighbours lie in two different iolets loses the higher-id iolet voxels
+    (they become wall)."""
+    for _ in range(8):
+        inner = lab[1:-1, 1:-1, 1:-1]
+        fl = inner == FLUID
+        lo = np.full(inner.shape, 255, np.uint8)
+        hi = np.zeros(inner.shape, np.uint8)
+        nz, ny, nx = lab.shape
+        for dx, dy, dz in _OFFS18:
+            nb = lab[1 - dz:nz - 1 - dz, 1 - dy:ny - 1 - dy, 1 - dx:nx - 1 - dx]
+            io = nb >= IOLET0
+            np.minimum(lo, np.where(io, nb, 255), out=lo)
+            np.maximum(hi, np.where(io, nb, 0), out=hi)
+        bad = fl & (hi > lo) & (lo < 255)
+        if not bad.any():
+            return
+        zz, yy, xx = np.nonzero(bad)
+        for z, y, x in zip(zz + 1, yy + 1, xx + 1):
+            h = hi[z - 1, y - 1, x - 1]
+            for dx, dy, dz in _OFFS18:
+                if lab[z - dz, y - dy, x - dx] == h:
+                    lab[z - dz, y - dy, x - dx] = WALL
+
+
+def murray_tree(seed: int, scale: float = 1.0, generations: int = 4, root_radius: float = 40.0,
+                box=(1200, 400, 400), angle_range=(30.0, 70.0), length_factor: float = 8.9,
+                stubs_per_leaf: int = 3, max_tries: int = 50, pull: float = 1.0):
+    """Bifurcating tapered tree with Murray's-law radii, r_g = r_root 2^(-g/3)
+    (each segment tapers by 2^(-1/6) along its length), segment lengths
+    length_factor r_g U(0.9, 1.1), branch angle (between daughters)
+    U(angle_range) about a downstream bisector pulled toward the box axis,
+    bifurcation planes turned 90 degrees per generation, and
+    at every leaf end a trifurcation into stubs of radius r 3^(-1/3) and length
+    4 r, each ending in a fixed-density outlet.  The root runs along +x from
+    the inlet plane x = 0.  Everything is scaled by ``scale``.  Returns the
+    Geometry with one segment id per tube; redraws until the tree fits the
+    box with a 4-voxel margin."""
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = (int(round(b * scale)) for b in box)
+    R0 = root_radius * scale
+    for _ in range(max_tries):
+        segs: List[Segment] = []
+        c = np.array([0.0, (ny - 1) / 2.0, (nz - 1) / 2.0])
+
+        def grow(p0, d, gen, normal):
+            r = R0 * 2.0 ** (-gen / 3.0)
+            L = length_factor * r * rng.uniform(0.9, 1.1)
+            r_end = r * 2.0 ** (-1.0 / 6.0)
+            p1 = p0 + d * L
+            s = Segment(p0=p0, p1=p1, r0=r, r1=r_end, gen=gen, inlet=(gen == 0),
+                        sid=len(segs))
+            segs.append(s)
+            if gen + 1 < generations + 1:
+                half = math.radians(rng.uniform(*angle_range)) / 2.0
+                # daughters at +-half about a bisector that runs downstream
+                # (+x) and is pulled back toward the box axis
+                lat = p1 - c
+                lat[0] = 0.0
+                b = np.array([1.0, 0.0, 0.0]) - pull * lat / (0.5 * min(ny, nz))
+                b /= np.linalg.norm(b)
+                nrm = _rot(normal, d, math.pi / 2.0)
+                nrm = nrm - (nrm @ b) * b
+                nrm /= np.linalg.norm(nrm)
+                for sgn in (+1, -1):
+                    grow(p1, _rot(b, nrm, sgn * half), gen + 1, nrm)
+            else:
+                rs = r_end * 3.0 ** (-1.0 / 3.0)
+                for k in range(stubs_per_leaf):
+                    ang = 2 * math.pi * k / stubs_per_leaf
+                    off = _rot(normal, d, ang)
+                    ds = d * math.cos(math.radians(35)) + off * math.sin(math.radians(35))
+                    ds /= np.linalg.norm(ds)
+                    segs.append(Segment(p0=p1, p1=p1 + ds * 4.0 * rs, r0=rs, r1=rs, gen=gen + 1,
+                                        outlet=True, sid=len(segs)))
+
+        grow(c, np.array([1.0, 0.0, 0.0]), 0, np.array([0.0, 1.0, 0.0]))
+        pts = np.array([s.p1 for s in segs] + [s.p0 for s in segs])
+        rad = max(s.r0 for s in segs[1:])
+        lo = pts.min(0) - rad - 4
+        hi = pts.max(0) + rad + 4
+        if lo[1] >= 0 and lo[2] >= 0 and hi[0] <= nx - 1 and hi[1] <= ny - 1 and hi[2] <= nz - 1:
+            break
+    else:
+        raise RuntimeError("tree does not fit the box")
+    # the root starts on the inlet plane: extend it back so x = 1 is inside
+    segs[0].p0 = segs[0].p0 - np.array([2.0, 0.0, 0.0])
+    g = voxelise(segs, (nz, ny, nx))
+    g.info = dict(kind="murray_tree", seed=seed, scale=scale, generations=generations,
+                  n_segments=len(segs), box=(nx, ny, nz))
+    g.segments = segs
+    return g
+
+
+def bifurcation(r: float, length: float, angle_deg: float, margin: int = 3) -> Geometry:
+    """Single bifurcation: a parent tube of radius r and length length/2
+    along +x from the inlet plane, two daughters of radius r 2^(-1/3) and
+    length length/2 at +-angle/2, each ending in a fixed-density outlet."""
+    rc = r * 2.0 ** (-1.0 / 3.0)
+    half = math.radians(angle_deg) / 2.0
+    Lp, Lc = length / 2.0, length / 2.0
+    p_end = np.array([Lp, 0.0, 0.0])
+    ends = [p_end + Lc * np.array([math.cos(half), s * math.sin(half), 0.0]) for s in (1, -1)]
+    ymax = max(abs(e[1]) for e in ends) + rc + margin + 2
+    nx = int(math.ceil(max(e[0] for e in ends) + rc + margin + 3))
+    ny = int(math.ceil(2 * max(ymax, r + margin + 2))) + 1
+    nz = int(math.ceil(2 * (r + margin + 2))) + 1
+    c = np.array([0.0, (ny - 1) / 2.0, (nz - 1) / 2.0])
+    segs = [Segment(p0=c - np.array([2.0, 0, 0]), p1=c + p_end, r0=r, r1=r, inlet=True, sid=0)]
+    for k, e in enumerate(ends):
+        segs.append(Segment(p0=c + p_end, p1=c + e, r0=rc, r1=rc, outlet=True, sid=k + 1))
+    g = voxelise(segs, (nz, ny, nx))
+    g.info = dict(kind="bifurcation", r=r, length=length, angle=angle_deg)
+    return g
+
+
+def straight_tube_x(r: float, length: float, margin: int = 3) -> Geometry:
+    """Straight tube along +x from the inlet plane x = 0, radius r, flat
+    outlet cap at the far end."""
+    n = int(math.ceil(2 * (r + margin + 2))) + 1
+    nx = int(math.ceil(length + margin + 4))
+    c = np.array([0.0, (n - 1) / 2.0, (n - 1) / 2.0])
+    segs = [Segment(p0=c - np.array([2.0, 0, 0]), p1=c + np.array([length, 0.0, 0.0]), r0=r,
+                    r1=r, inlet=True, outlet=True, sid=0)]
+    g = voxelise(segs, (n, n, nx))
+    g.info = dict(kind="tube", r=r, length=length)
+    return g
+
+
+def batch(seed: int, n: int = 64, target_sites: float = 20e6, r_range=(6.0, 24.0),
+          lr_range=(8.0, 16.0), angle_range=(30.0, 70.0), k_range=(1e-3, 1e-1),
+          u0_range=(0.01, 0.03), tol: float = 0.05):
+    """Uneven batch: half straight tubes, half single bifurcations, radius
+    U(r_range), length/radius U(lr_range); all lengths are then scaled by
+    one common factor so that the total site count is target_sites within
+    tol (the stated radius and length distributions alone give about 12M
+    sites for 64 instances).  Per instance: stiffness log-uniform in
+    k_range, inlet amplitude U(u0_range).  Returns (geometries, params)."""
+    rng = np.random.default_rng(seed)
+    kinds = ["tube"] * (n // 2) + ["bif"] * (n - n // 2)
+    rng.shuffle(kinds)
+    r = rng.uniform(*r_range, size=n)
+    lr = rng.uniform(*lr_range, size=n)
+    ang = rng.uniform(*angle_range, size=n)
+    k = log_uniform(rng, *k_range, size=n)
+    u0 = rng.uniform(*u0_range, size=n)
+
+    def est(kind, ri, Li):  # volume estimate
+        if kind == "tube":
+            return math.pi * ri * ri * Li
+        rc = ri * 2 ** (-1 / 3)
+        return math.pi * ri * ri * Li / 2 + 2 * math.pi * rc * rc * Li / 2
+
+    base = sum(est(kd, ri, ri * li) for kd, ri, li in zip(kinds, r, lr))
+    s = target_sites / base if target_sites else 1.0
+    for _ in range(6):
+        geos = []
+        for kd, ri, li, ai in zip(kinds, r, lr, ang):
+            L = ri * li * s
+            geos.append(straight_tube_x(ri, L) if kd == "tube" else bifurcation(ri, L, ai))
+        tot = sum(g.n_fluid for g in geos)
+        if not target_sites or abs(tot / target_sites - 1) <= tol:
+            break
+        s *= target_sites / tot
+    params = [dict(kind=kd, r=float(ri), length=float(ri * li * s), angle=float(ai), k=float(ki),
+                   u0=float(ui)) for kd, ri, li, ai, ki, ui in zip(kinds, r, lr, ang, k, u0)]
+    return geos, params

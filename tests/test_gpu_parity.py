@@ -230,3 +230,50 @@ def test_full_size_tube_parity_short_run():
     record("tube32_full_size", e, dtype="f32", steps=24, launch=lat.info())
     assert e["u"] <= 1e-5 and e["p"] <= 1e-5
     lat.close()
+
+
+def _tree_problem(scale, seed=3):
+    g = inputs.murray_tree(seed, scale=scale)
+    rng = np.random.default_rng(seed)
+    k = list(inputs.log_uniform(rng, 1e-3, 1e-1, size=g.n_seg))
+    inlet_dir = g.iolets[0]["direction"]
+    io = {0: dict(kind=lbm.VELOCITY, a0=0.02, amp=0.5, period=400.0, direction=inlet_dir)}
+    for d in g.iolets[1:]:
+        io[d["id"]] = dict(kind=lbm.DENSITY, a0=1.0)
+    return H.Problem(geo=g, tau=0.8, mode=lbm.ELASTIC, F=0.5, P0=1.0 / 3.0, k=k, iolets=io)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16"])
+def test_quarter_scale_tree(dtype):
+    """Quarter-scale Murray tree (about 105k sites, 79 stiffness segments,
+    48 outlets), elastic walls, pulsatile inlet, 600 steps."""
+    p = _tree_problem(0.25)
+    g, r = run_pair(p, dtype, 600)
+    e = H.errors(g, r, P0=p.P0)
+    record("tree_quarter", e, dtype=dtype, steps=600)
+    bound = {"f32": 1e-5, "f16": 1e-2}[dtype]
+    assert e["u"] <= bound and e["p"] <= bound
+
+
+def test_batch_of_tubes_and_bifurcations():
+    """Four instances drawn like the 64-instance sweep (tubes and single
+    bifurcations, per-instance stiffness and inlet amplitude), FP32."""
+    geos, params = inputs.batch(8, n=4, target_sites=2.5e5)
+    probs = []
+    for g, q in zip(geos, params):
+        io = {0: dict(kind=lbm.VELOCITY, a0=q["u0"], amp=0.5, period=300.0,
+                      direction=g.iolets[0]["direction"])}
+        for d in g.iolets[1:]:
+            io[d["id"]] = dict(kind=lbm.DENSITY, a0=1.0)
+        probs.append(H.Problem(geo=g, tau=0.8, mode=lbm.ELASTIC, F=0.5, P0=1.0 / 3.0,
+                               k=[q["k"]] * g.n_seg, iolets=io))
+    lat = H.make_lattice(probs, "f32")
+    lat.autotune(16)
+    lat.step(500)
+    for k, p in enumerate(probs):
+        o = H.make_oracle(p)
+        o.step(500)
+        e = H.errors(lat.read_fields(k), o.read(), P0=p.P0)
+        record(f"sweep_inst{k}", e, dtype="f32", steps=500)
+        assert e["u"] <= 1e-5 and e["p"] <= 1e-5
+    lat.close()
