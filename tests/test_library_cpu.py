@@ -33,6 +33,16 @@ def test_library_exports_every_declared_symbol():
         assert ctypes.cast(getattr(lib, name), ctypes.c_void_p).value
 
 
+def test_library_exports_every_network_symbol():
+    from paper_2108_08783_amd import mlp
+    lib = mlp.load()
+    text = open(os.path.join(ROOT, "include", "lbm_mlp.h")).read()
+    declared = sorted(set(re.findall(r"^(?:int|int64_t|const char\*)\s+(mlp_\w+)\s*\(", text, re.M)))
+    assert declared == sorted(mlp.MLP_EXPORTS)
+    for name in declared:
+        assert ctypes.cast(getattr(lib, name), ctypes.c_void_p).value
+
+
 def test_cylinder_counts_match_independent_voxelisation():
     # independent counts of the R=8, L=64 and R=32, L=512 tubes (site,
     # boundary-site, wall-link and iolet-link numbers of the same shape).
