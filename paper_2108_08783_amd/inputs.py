@@ -26,6 +26,7 @@ WALL, FLUID, IOLET0 = 0, 1, 2
 @dataclasses.dataclass
 class Geometry:
     labels: np.ndarray                      # uint8 [nz, ny, nx]
+    segments: Optional[list] = None         # tube segments the shape was built from
     segment: Optional[np.ndarray] = None    # uint16 [nz, ny, nx]
     normal: Optional[np.ndarray] = None     # float32 [nz, ny, nx, 3], outward unit
     iolet_weight: Optional[np.ndarray] = None  # float32 [nz, ny, nx]
@@ -277,6 +278,7 @@ def voxelise(segments: List[Segment], shape, iolet_of_segment=None) -> Geometry:
     _resolve_iolet_conflicts(lab)
     g = Geometry(labels=lab, segment=seg, iolet_weight=iw, n_seg=len(segments))
     g.iolets = iolets
+    g.segments = list(segments)
     return g
 
 
@@ -287,8 +289,24 @@ _OFFS18 = [(dx, dy, dz) for dx in (-1, 0, 1) for dy in (-1, 0, 1) for dz in (-1,
 def _resolve_iolet_conflicts(lab):
     """Vectorised form of separate_iolets: a fluid voxel whose upstream
     neighbours lie in two different iolets loses the higher-id iolet voxels
-    (they become wall)."""
+    (they become wall).  Only the neighbourhoods of iolet voxels are
+    examined."""
+    zz, yy, xx = np.nonzero(lab >= IOLET0)
+    if len(zz) == 0:
+        return
+    nz, ny, nx = lab.shape
+    ids = lab[zz, yy, xx]
+    for v in np.unique(ids):
+        sel = ids == v
+        lo = np.maximum([zz[sel].min() - 3, yy[sel].min() - 3, xx[sel].min() - 3], 0)
+        hi = np.minimum([zz[sel].max() + 4, yy[sel].max() + 4, xx[sel].max() + 4], [nz, ny, nx])
+        _resolve_region(lab[lo[0]:hi[0], lo[1]:hi[1], lo[2]:hi[2]])
+
+
+def _resolve_region(lab):
     for _ in range(8):
+        if min(lab.shape) < 3:
+            return
         inner = lab[1:-1, 1:-1, 1:-1]
         fl = inner == FLUID
         lo = np.full(inner.shape, 255, np.uint8)
@@ -375,7 +393,6 @@ def murray_tree(seed: int, scale: float = 1.0, generations: int = 4, root_radius
     g = voxelise(segs, (nz, ny, nx))
     g.info = dict(kind="murray_tree", seed=seed, scale=scale, generations=generations,
                   n_segments=len(segs), box=(nx, ny, nz))
-    g.segments = segs
     return g
 
 
@@ -395,7 +412,7 @@ def bifurcation(r: float, length: float, angle_deg: float, margin: int = 3) -> G
     c = np.array([0.0, (ny - 1) / 2.0, (nz - 1) / 2.0])
     segs = [Segment(p0=c - np.array([2.0, 0, 0]), p1=c + p_end, r0=r, r1=r, inlet=True, sid=0)]
     for k, e in enumerate(ends):
-        segs.append(Segment(p0=c + p_end, p1=c + e, r0=rc, r1=rc, outlet=True, sid=k + 1))
+        segs.append(Segment(p0=c + p_end, p1=c + e, r0=rc, r1=rc, gen=1, outlet=True, sid=k + 1))
     g = voxelise(segs, (nz, ny, nx))
     g.info = dict(kind="bifurcation", r=r, length=length, angle=angle_deg)
     return g

@@ -76,6 +76,13 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is not built: run paper_2108_08783_amd/build.py "
                            "(or __graft_entry__.build()) first")
+    # torch ships its own HIP runtime; load it first so that the library and
+    # torch share one runtime in the process (the library's dependency is
+    # then resolved to the already-loaded copy).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     P, I, D, L = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_int64
     sig = {

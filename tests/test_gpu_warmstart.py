@@ -1,0 +1,40 @@
+"""Learned warm start, end to end at reduced scale: the network is trained
+on cold-started periodic states of small sweep instances, then warm and
+cold starts of held-out instances must reach the same periodic state, and
+the warm start must not need more cycles on average."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def test_init_fields_device_matches_host_init():
+    import torch
+    from paper_2108_08783_amd import workloads
+    wl = workloads.sweep(seed=21, n=2, target_sites=4e4)
+    n = wl.geoms[1].n_fluid
+    rng = np.random.default_rng(0)
+    rho = 1 + 1e-3 * rng.uniform(-1, 1, n)
+    u = 0.01 * rng.uniform(-1, 1, (n, 3))
+    a = workloads.lattice(wl, "f32")
+    b = workloads.lattice(wl, "f32")
+    a.init_fields(1, rho, u)
+    ru = torch.tensor(np.concatenate([rho[:, None], u], 1), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    b.init_fields_device(1, ru)
+    fa, fb = a.read_populations(1), b.read_populations(1)
+    assert np.abs(fa - fb).max() <= 1e-7      # FP32 inputs vs FP64 inputs
+    a.close()
+    b.close()
+
+
+def test_warm_start_reaches_the_cold_periodic_state_in_fewer_cycles():
+    from paper_2108_08783_amd import warmstart
+    r = warmstart.experiment(train_batches=1, train_per_batch=16, train_sites=1.5e6,
+                             test_sweep=6, test_sweep_sites=6e5, test_trees=1, tree_scale=0.25,
+                             epochs=25, sites_per_phase=1024, log=print)
+    print({k: v for k, v in r.items() if k != "results"})
+    assert r["all_converged"]
+    assert r["loss_last"] < r["loss_first"] / 5
+    assert r["max_state_diff"] <= 2e-3
+    assert r["cycles_warm_mean"] <= r["cycles_cold_mean"]
