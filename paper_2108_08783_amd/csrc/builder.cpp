@@ -1,6 +1,7 @@
 // Host-side geometry plan (see builder.hpp).
 #include "builder.hpp"
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <sstream>
@@ -138,22 +139,98 @@ void build_boundary(const Plan& plan, const std::vector<int>& mode,
                     BoundaryList& out) {
     out = BoundaryList();
     const int64_t N = plan.N;
+    out.rec_of_site.assign(N, -1);
     for (int64_t x = 0; x < N; ++x) {
         const uint32_t k = plan.site_inst[x];
         uint32_t wmask = 0, imask = 0;
+        bool irregular = false;
         for (int i = 1; i < Q; ++i) {
             const int32_t c = plan.nbr[(size_t)(i - 1) * N + x];
+            if (c == H_WALL || c == H_IOLET) irregular = true;
             if (c == H_WALL && mode[k] == LBM_WALL_ELASTIC) wmask |= 1u << i;
             if (c == H_IOLET) imask |= 1u << i;
         }
-        if (!(wmask | imask)) continue;
+        if (!irregular) continue;
+        const int32_t id = (int32_t)out.site.size();
+        out.rec_of_site[x] = id;
         out.site.push_back((int32_t)x);
         out.wall.push_back(wmask | (k << 19));
         const uint32_t slot = imask ? (uint32_t)(iolet_off[k] + plan.site_iolet[x]) : 0u;
         out.io.push_back(imask | (slot << 19));
         out.kidx.push_back(seg_off[k] + plan.site_seg[x]);
         out.weight.push_back(plan.site_w[x]);
+        if (wmask | imask) out.ghost.push_back(id);
     }
+}
+
+std::string build_compressed(const Plan& plan, const BoundaryList& bl,
+                             const std::vector<int32_t>& nbr_dev32, int64_t n_pad, Compressed& out) {
+    out = Compressed();
+    const int64_t N = plan.N;
+    const int64_t nwf = n_pad / 64;
+    out.wf_cur.assign(nwf, -1);
+    out.wf_firr.assign(nwf, 0);
+    out.wf_smask.assign(nwf, 0);
+    out.wf_imask.assign(nwf, 0);
+    out.n_irr = (int64_t)bl.site.size();
+    out.n_irr_pad = (out.n_irr + 255) / 256 * 256;
+    out.irr.assign((size_t)18 * std::max<int64_t>(out.n_irr_pad, 256), 0);
+    for (int64_t j = 0; j < out.n_irr; ++j) {
+        const int32_t x = bl.site[j];
+        for (int i = 0; i < 18; ++i) out.irr[(size_t)i * out.n_irr_pad + j] = nbr_dev32[(size_t)i * n_pad + x];
+    }
+    int32_t cur = -1, nirr = 0;
+    bool prev_interior = false;
+    int32_t prevD[8] = {0};
+    for (int64_t w = 0; w < nwf; ++w) {
+        out.wf_cur[w] = cur;
+        out.wf_firr[w] = nirr;
+        uint64_t sm = 0, im = 0;
+        for (int l = 0; l < 64; ++l) {
+            const int64_t x = w * 64 + l;
+            if (x >= N) break;
+            if (bl.rec_of_site[x] >= 0) {
+                im |= 1ull << l;
+                ++nirr;
+                prev_interior = false;
+                continue;
+            }
+            int32_t D[8];
+            for (int r = 0; r < 8; ++r) {
+                // the direction whose upstream voxel is (x, y+dy, z+dz): c = (0, -dy, -dz)
+                int dir = -1;
+                for (int i = 1; i < Q; ++i)
+                    if (CX[i] == 0 && CY[i] == -ROW8[r][0] && CZ[i] == -ROW8[r][1]) dir = i;
+                D[r] = plan.nbr[(size_t)(dir - 1) * N + x];
+            }
+            // the derived offsets must reproduce the site's table exactly
+            for (int i = 1; i < Q; ++i) {
+                int32_t d;
+                if (CY[i] == 0 && CZ[i] == 0) {
+                    d = -CX[i];
+                } else {
+                    int r = 0;
+                    while (!(ROW8[r][0] == -CY[i] && ROW8[r][1] == -CZ[i])) ++r;
+                    d = D[r] - CX[i];
+                }
+                if (d != plan.nbr[(size_t)(i - 1) * N + x])
+                    return "compressed addressing: derived offset mismatch at site " +
+                           std::to_string(x);
+            }
+            if (!prev_interior || std::memcmp(D, prevD, sizeof(D)) != 0) {
+                ++cur;
+                out.stretch.insert(out.stretch.end(), D, D + 8);
+                sm |= 1ull << l;
+                std::memcpy(prevD, D, sizeof(D));
+            }
+            prev_interior = true;
+        }
+        out.wf_smask[w] = sm;
+        out.wf_imask[w] = im;
+    }
+    out.n_stretch = cur + 1;
+    if (out.stretch.empty()) out.stretch.assign(8, 0);
+    return "";
 }
 
 template <typename I>

@@ -44,20 +44,52 @@ struct Plan {
 // Returns an empty string on success, else the reason.
 std::string build_plan(const lbm_instance_desc* desc, int n_inst, Plan& plan);
 
-// The boundary list for a given wall mode per instance (0 bounce-back,
-// 1 elastic): sites having at least one link handled by the boundary pass
-// (elastic wall link or iolet link).
+// Irregular sites: every site with at least one non-fluid link, in site
+// order.  Each carries a boundary record; the records with elastic-wall or
+// iolet links (the boundary pass) are listed in `ghost`.  The wall mode per
+// instance (0 bounce-back, 1 elastic) decides which wall links are
+// bounce-back redirects and which go through the boundary rule.
 struct BoundaryList {
-    std::vector<int32_t> site;
+    std::vector<int32_t> site;    // irregular site indices
     std::vector<uint32_t> wall;   // bits 1..18 elastic wall links | inst << 19
     std::vector<uint32_t> io;     // bits 1..18 iolet links | global iolet slot << 19
     std::vector<int32_t> kidx;    // index into the global stiffness table
     std::vector<float> weight;    // iolet profile weight
+    std::vector<int32_t> ghost;   // record ids with boundary-pass links
+    std::vector<int32_t> rec_of_site;  // per site: record id or -1
 };
 
 void build_boundary(const Plan& plan, const std::vector<int>& mode,
                     const std::vector<int>& seg_off, const std::vector<int>& iolet_off,
                     BoundaryList& out);
+
+// Compressed addressing.  Offsets of an interior site (all 18 upstream
+// voxels fluid) follow from the 8 offsets d(dy,dz) to the voxel at the same
+// x in the neighbouring rows (y+dy, z+dz): the upstream voxel of direction
+// c is at d(-cy,-cz) - cx (x-neighbours in a row are consecutive sites).
+// Along a run of consecutive interior sites in one row these 8 offsets are
+// constant (a "stretch").  Per wavefront of 64 consecutive sites:
+//   cur    id of the stretch of the last interior site before the wavefront
+//   firr   id of the first irregular site at or after the wavefront start
+//   smask  bit l: site l starts a new stretch
+//   imask  bit l: site l is irregular
+// so stretch(l) = cur + popcount(smask & bits 0..l) and
+// irregular id(l) = firr + popcount(imask & bits 0..l-1).  Irregular sites
+// keep all 18 offsets (32-bit, with the sentinels of Sentinel<int32_t>).
+struct Compressed {
+    std::vector<int32_t> wf_cur, wf_firr;
+    std::vector<uint64_t> wf_smask, wf_imask;
+    std::vector<int32_t> stretch;  // 8 per stretch, (dy,dz) in order of ROW8
+    std::vector<int32_t> irr;      // 18 planes x n_irr_pad
+    int64_t n_irr = 0, n_irr_pad = 0, n_stretch = 0;
+};
+
+// (dy, dz) of the 8 neighbouring rows, in stretch-table order.
+constexpr int ROW8[8][2] = {{1, 0}, {-1, 0}, {0, 1}, {0, -1}, {1, 1}, {-1, -1}, {1, -1}, {-1, 1}};
+
+// Returns an empty string on success.
+std::string build_compressed(const Plan& plan, const BoundaryList& bl,
+                             const std::vector<int32_t>& nbr_dev32, int64_t n_pad, Compressed& out);
 
 // Device neighbour table of width I for the given wall modes.
 template <typename I>

@@ -12,6 +12,8 @@
 // Sec. 3).  Every slot is read by exactly one site per step.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "../../include/lbm.h"
 #include "d3q19.hpp"
 #include "kernels.hpp"
@@ -91,6 +93,60 @@ __device__ __forceinline__ void gather(const typename Codec<DT>::raw* __restrict
         const bool redirect = di <= Sentinel<I>::GHOST;
         const int64_t idx = redirect ? (int64_t)dopp(i) * np + x : (int64_t)i * np + x + di;
         h[i] = Codec<DT>::dec(A[idx]);
+    }
+}
+
+// Slot of the 8-entry stretch table holding the row (y - cy, z - cz) of
+// direction i (rows in the order (1,0),(-1,0),(0,1),(0,-1),(1,1),(-1,-1),
+// (1,-1),(-1,1) of (dy,dz)); -1 for the same row.
+__device__ __forceinline__ constexpr int row_slot(int i) {
+    return (CY[i] == 0 && CZ[i] == 0) ? -1
+         : (CY[i] == -1 && CZ[i] == 0) ? 0
+         : (CY[i] == 1 && CZ[i] == 0) ? 1
+         : (CY[i] == 0 && CZ[i] == -1) ? 2
+         : (CY[i] == 0 && CZ[i] == 1) ? 3
+         : (CY[i] == -1 && CZ[i] == -1) ? 4
+         : (CY[i] == 1 && CZ[i] == 1) ? 5
+         : (CY[i] == -1 && CZ[i] == 1) ? 6 : 7;
+}
+
+// Neighbour offsets of site x (32-bit, table sentinels) and its boundary
+// record id (-1 for interior sites; only looked up by sites with
+// boundary-pass links in table addressing).
+template <int ADDR>
+__device__ __forceinline__ void site_offsets(const StepArgs& a, int x, int32_t (&d)[18], int& rec) {
+    if constexpr (ADDR == ADDR_COMP) {
+        const int w = x >> 6, l = x & 63;
+        const uint64_t im = a.wf_imask[w];
+        if ((im >> l) & 1ull) {
+            const int id = a.wf_firr[w] + __popcll(im & ((1ull << l) - 1ull));
+            rec = id;
+#pragma unroll
+            for (int i = 0; i < 18; ++i) d[i] = a.irr[(int64_t)i * a.n_irr_pad + id];
+        } else {
+            rec = -1;
+            const int st = a.wf_cur[w] + __popcll(a.wf_smask[w] & (~0ull >> (63 - l)));
+            const int4* S = (const int4*)(a.stretch + 8 * (int64_t)st);
+            const int4 s0 = S[0], s1 = S[1];
+            const int D[8] = {s0.x, s0.y, s0.z, s0.w, s1.x, s1.y, s1.z, s1.w};
+#pragma unroll
+            for (int i = 1; i < Q; ++i) {
+                const int r = row_slot(i);
+                d[i - 1] = (r < 0 ? 0 : D[r]) - CX[i];
+            }
+        }
+    } else {
+        using I = typename std::conditional<ADDR == ADDR_T16, int16_t, int32_t>::type;
+        const I* nbr = (const I*)a.nbr;
+        bool ghost = false;
+#pragma unroll
+        for (int i = 0; i < 18; ++i) {
+            const I v = nbr[(int64_t)i * a.np + x];
+            d[i] = v == Sentinel<I>::BB ? Sentinel<int32_t>::BB
+                 : v == Sentinel<I>::GHOST ? Sentinel<int32_t>::GHOST : (int32_t)v;
+            ghost |= v == Sentinel<I>::GHOST;
+        }
+        rec = ghost ? a.bidx[x] : -1;
     }
 }
 
@@ -240,23 +296,25 @@ __device__ __forceinline__ void apply_links(const StepArgs& a, int j, const Mom<
 }
 
 // One site: pull, BGK collision (Sec. 2.1 eq. LBE_SRT) and store.  A site
-// with boundary-pass links either returns (compacted mode: the boundary
-// blocks update it) or applies the link rules in place (fused mode), using
-// its boundary record from bidx.
-template <int DT, typename I>
-__device__ __forceinline__ void update_site(const StepArgs& a, int x, int j_compact) {
+// with boundary-pass links either returns (compacted mode, when called from
+// the update blocks: the boundary blocks update it) or applies the link
+// rules of its boundary record in place (fused mode, and the boundary
+// blocks of the compacted mode).
+template <int DT, int ADDR>
+__device__ __forceinline__ void update_site(const StepArgs& a, int x, bool from_boundary_blocks) {
     using raw = typename Codec<DT>::raw;
     using acc = typename Codec<DT>::acc;
     const raw* __restrict__ A = (const raw*)a.A;
     raw* __restrict__ B = (raw*)a.B;
-    I d[18];
-    load_offsets<I>((const I*)a.nbr, a.np, x, d);
+    int32_t d[18];
+    int rec;
+    site_offsets<ADDR>(a, x, d, rec);
     bool ghost = false;
 #pragma unroll
-    for (int i = 0; i < 18; ++i) ghost |= (d[i] == Sentinel<I>::GHOST);
-    if (ghost && j_compact < 0 && !a.fused) return;  // updated by the boundary blocks
+    for (int i = 0; i < 18; ++i) ghost |= (d[i] == Sentinel<int32_t>::GHOST);
+    if (ghost && !from_boundary_blocks && !a.fused) return;
     acc h[Q];
-    gather<DT, I>(A, a.np, x, d, h);
+    gather<DT, int32_t>(A, a.np, x, d, h);
     const Mom<acc> m = moments(h);
     acc e[Q];
     heq(m.drho, m.rho, m.ux, m.uy, m.uz, e);
@@ -268,23 +326,23 @@ __device__ __forceinline__ void update_site(const StepArgs& a, int x, int j_comp
         const acc hs[Q] = {out[0], out[1], out[2], out[3], out[4], out[5], out[6],
                            out[7], out[8], out[9], out[10], out[11], out[12],
                            out[13], out[14], out[15], out[16], out[17], out[18]};
-        apply_links<acc>(a, j_compact >= 0 ? j_compact : a.bidx[x], m, e, hs, out);
+        apply_links<acc>(a, rec, m, e, hs, out);
     }
     const bool nt = a.nontemporal != 0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) put(B + (int64_t)i * a.np + x, Codec<DT>::enc(out[i]), nt);
 }
 
-template <int DT, typename I>
+template <int DT, int ADDR>
 __global__ __launch_bounds__(1024) void k_step(StepArgs a) {
     const int b = blockIdx.x;
     if (b < a.n_int_blocks) {
         const int lb = a.xcd_remap ? remap_xcd(b, a.n_int_blocks) : b;
         const int x = lb * (int)blockDim.x + (int)threadIdx.x;
-        if (x < a.n) update_site<DT, I>(a, x, -1);
+        if (x < a.n) update_site<DT, ADDR>(a, x, false);
     } else {
         const int j = (b - a.n_int_blocks) * (int)blockDim.x + (int)threadIdx.x;
-        if (j < a.nb) update_site<DT, I>(a, a.bsite[j], j);
+        if (j < a.nb) update_site<DT, ADDR>(a, a.rsite[a.bj[j]], true);
     }
     if (b == 0 && threadIdx.x == 0) a.clock[a.clock_in ^ 1] = a.clock[a.clock_in] + 1;
 }
@@ -481,14 +539,23 @@ hipError_t dispatch(int dtype, int ibits, Args&&... args) {
     return hipErrorInvalidValue;
 }
 
-template <int DT, typename I>
-struct StepL {
-    static hipError_t run(const StepArgs& a, int block, hipStream_t s) {
-        const int nblk = a.n_int_blocks + (a.fused ? 0 : cdiv(a.nb, block));
-        hipLaunchKernelGGL((k_step<DT, I>), dim3(nblk), dim3(block), 0, s, a);
-        return hipGetLastError();
+template <int DT, int ADDR>
+hipError_t step_launch(const StepArgs& a, int block, hipStream_t s) {
+    const int nblk = a.n_int_blocks + (a.fused ? 0 : cdiv(a.nb, block));
+    hipLaunchKernelGGL((k_step<DT, ADDR>), dim3(nblk), dim3(block), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int DT>
+hipError_t step_addr(int addressing, const StepArgs& a, int block, hipStream_t s) {
+    switch (addressing) {
+        case ADDR_T16: return step_launch<DT, ADDR_T16>(a, block, s);
+        case ADDR_T32: return step_launch<DT, ADDR_T32>(a, block, s);
+        case ADDR_COMP: return step_launch<DT, ADDR_COMP>(a, block, s);
     }
-};
+    return hipErrorInvalidValue;
+}
+
 template <int DT, typename I>
 struct FieldsL {
     static hipError_t run(const FieldArgs& a, hipStream_t s) {
@@ -532,8 +599,14 @@ struct DeltaL {
 
 }  // namespace
 
-hipError_t launch_step(int dtype, int ibits, const StepArgs& a, int block, hipStream_t s) {
-    return dispatch<StepL>(dtype, ibits, a, block, s);
+hipError_t launch_step(int dtype, int addressing, const StepArgs& a, int block, hipStream_t s) {
+    switch (dtype) {
+        case LBM_F64: return step_addr<LBM_F64>(addressing, a, block, s);
+        case LBM_F32: return step_addr<LBM_F32>(addressing, a, block, s);
+        case LBM_F16DEV: return step_addr<LBM_F16DEV>(addressing, a, block, s);
+        case LBM_BF16DEV: return step_addr<LBM_BF16DEV>(addressing, a, block, s);
+    }
+    return hipErrorInvalidValue;
 }
 hipError_t launch_fields(int dtype, int ibits, const FieldArgs& a, hipStream_t s) {
     return dispatch<FieldsL>(dtype, ibits, a, s);

@@ -39,8 +39,9 @@ struct StepArgs {
     int32_t fused;          // 1: boundary links applied inside the update blocks
     int32_t pad;
     double omega;           // 1 / tau
-    const int32_t* bsite;
-    const int32_t* bidx;    // per site: boundary record index (fused mode)
+    const int32_t* bj;      // record ids of sites with boundary-pass links (compacted mode)
+    const int32_t* rsite;   // record id -> site
+    const int32_t* bidx;    // per site: record id, -1 for interior sites (table addressing)
     const uint32_t* bwall;  // elastic wall link mask | inst << 19
     const uint32_t* bio;    // iolet link mask | iolet slot << 19
     const int32_t* bk;      // stiffness index
@@ -49,7 +50,19 @@ struct StepArgs {
     const IoletParams* iop;
     const double* kinv;     // 1 / k per stiffness index
     int64_t* clock;         // [2] steps executed before the current one
+    // compressed addressing (see Compressed in builder.hpp)
+    const int32_t* wf_cur;
+    const int32_t* wf_firr;
+    const uint64_t* wf_smask;
+    const uint64_t* wf_imask;
+    const int32_t* stretch;  // 8 per stretch
+    const int32_t* irr;      // 18 planes x n_irr_pad
+    int64_t n_irr_pad;
 };
+
+// Addressing of the update kernel: per-site offset table of 16 or 32 bits,
+// or compressed (stretches + irregular-site table).
+enum { ADDR_T16 = 16, ADDR_T32 = 32, ADDR_COMP = 0 };
 
 struct FieldArgs {
     const void* A;
@@ -111,7 +124,7 @@ struct DeltaArgs {
 };
 
 // Launchers (kernels.hip).  dtype: enum lbm_dtype; ibits: 16 or 32.
-hipError_t launch_step(int dtype, int ibits, const StepArgs& a, int block, hipStream_t s);
+hipError_t launch_step(int dtype, int addressing, const StepArgs& a, int block, hipStream_t s);
 hipError_t launch_fields(int dtype, int ibits, const FieldArgs& a, hipStream_t s);
 hipError_t launch_wall(int dtype, int ibits, const WallArgs& a, hipStream_t s);
 hipError_t launch_init(int dtype, int ibits, const InitArgs& a, hipStream_t s);

@@ -73,13 +73,23 @@ struct lbm_ctx {
     void* nbr32 = nullptr;
     void* nbr16 = nullptr;
     bool have16 = false;
-    int32_t* bsite = nullptr;
-    int32_t* bidx = nullptr;   // per site: boundary record index, -1 if none
+    // boundary records, one per irregular site (any non-fluid link)
+    int32_t* bj = nullptr;     // record ids with boundary-pass links
+    int32_t* rsite = nullptr;  // record id -> site
+    int32_t* bidx = nullptr;   // per site: record id, -1 if interior
     uint32_t* bwall = nullptr;
     uint32_t* bio = nullptr;
     int32_t* bk = nullptr;
     float* bw = nullptr;
-    int64_t nb = 0, nb_cap = 0;
+    int64_t nb = 0, n_irr = 0;
+    // compressed addressing
+    int32_t* wf_cur = nullptr;
+    int32_t* wf_firr = nullptr;
+    uint64_t* wf_smask = nullptr;
+    uint64_t* wf_imask = nullptr;
+    int32_t* stretch = nullptr;
+    int32_t* irr = nullptr;
+    int64_t n_irr_pad = 0, n_stretch = 0;
     int32_t* wsite = nullptr;
     double* wnormal = nullptr;
     int32_t* wk = nullptr;
@@ -194,33 +204,32 @@ int sync_tables(lbm_ctx* c) {
         int rc = upload(c, c->nbr16, t16.data(), t16.size() * 2);
         if (rc) return rc;
     }
+    std::vector<int32_t> t32;
+    build_device_nbr<int32_t>(c->plan, m, c->np, t32);
     BoundaryList bl;
     build_boundary(c->plan, m, c->seg_off, c->iolet_off, bl);
-    const int64_t nb = (int64_t)bl.site.size();
-    if (nb > c->nb_cap) {
-        dfree(c, c->bsite); dfree(c, c->bwall); dfree(c, c->bio); dfree(c, c->bk); dfree(c, c->bw);
-        int rc = 0;
-        rc |= dalloc(c, (void**)&c->bsite, nb * 4);
-        rc |= dalloc(c, (void**)&c->bwall, nb * 4);
-        rc |= dalloc(c, (void**)&c->bio, nb * 4);
-        rc |= dalloc(c, (void**)&c->bk, nb * 4);
-        rc |= dalloc(c, (void**)&c->bw, nb * 4);
-        if (rc) return LBM_ENOMEM;
-        c->nb_cap = nb;
-    }
-    c->nb = nb;
-    int rc = upload(c, c->bsite, bl.site.data(), nb * 4);
-    rc = rc ? rc : upload(c, c->bwall, bl.wall.data(), nb * 4);
-    rc = rc ? rc : upload(c, c->bio, bl.io.data(), nb * 4);
-    rc = rc ? rc : upload(c, c->bk, bl.kidx.data(), nb * 4);
-    rc = rc ? rc : upload(c, c->bw, bl.weight.data(), nb * 4);
+    Compressed cm;
+    std::string e = build_compressed(c->plan, bl, t32, c->np, cm);
+    if (!e.empty()) return fail(c, LBM_EINVAL, "%s", e.c_str());
+    if ((int64_t)bl.site.size() != c->n_irr || cm.n_stretch != c->n_stretch)
+        return fail(c, LBM_ESTATE, "irregular-site set changed");
+    const int64_t ni = c->n_irr;
+    c->nb = (int64_t)bl.ghost.size();
+    int rc = upload(c, c->bj, bl.ghost.data(), c->nb * 4);
+    rc = rc ? rc : upload(c, c->rsite, bl.site.data(), ni * 4);
+    rc = rc ? rc : upload(c, c->bidx, bl.rec_of_site.data(), c->plan.N * 4);
+    rc = rc ? rc : upload(c, c->bwall, bl.wall.data(), ni * 4);
+    rc = rc ? rc : upload(c, c->bio, bl.io.data(), ni * 4);
+    rc = rc ? rc : upload(c, c->bk, bl.kidx.data(), ni * 4);
+    rc = rc ? rc : upload(c, c->bw, bl.weight.data(), ni * 4);
+    const int64_t nwf = c->np / 64;
+    rc = rc ? rc : upload(c, c->wf_cur, cm.wf_cur.data(), nwf * 4);
+    rc = rc ? rc : upload(c, c->wf_firr, cm.wf_firr.data(), nwf * 4);
+    rc = rc ? rc : upload(c, c->wf_smask, cm.wf_smask.data(), nwf * 8);
+    rc = rc ? rc : upload(c, c->wf_imask, cm.wf_imask.data(), nwf * 8);
+    rc = rc ? rc : upload(c, c->stretch, cm.stretch.data(), cm.stretch.size() * 4);
+    rc = rc ? rc : upload(c, c->irr, cm.irr.data(), cm.irr.size() * 4);
     if (rc) return rc;
-    {
-        std::vector<int32_t> bidx(c->plan.N, -1);
-        for (int64_t j = 0; j < nb; ++j) bidx[bl.site[j]] = (int32_t)j;
-        rc = upload(c, c->bidx, bidx.data(), bidx.size() * 4);
-        if (rc) return rc;
-    }
     c->tables_dirty = false;
     drop_graphs(c);
     return LBM_OK;
@@ -263,6 +272,8 @@ int check_ready(lbm_ctx* c) {
 }
 
 const void* nbr_ptr(const lbm_ctx* c) { return c->ibits == 16 ? c->nbr16 : c->nbr32; }
+// read-out, initialisation and checkpoint kernels always use the 32-bit table
+const void* nbr_rd(const lbm_ctx* c) { return c->nbr32; }
 
 StepArgs step_args(const lbm_ctx* c, int parity) {
     StepArgs a;
@@ -279,7 +290,8 @@ StepArgs step_args(const lbm_ctx* c, int parity) {
     a.fused = c->fused;
     a.pad = 0;
     a.omega = 1.0 / c->tau;
-    a.bsite = c->bsite;
+    a.bj = c->bj;
+    a.rsite = c->rsite;
     a.bidx = c->bidx;
     a.bwall = c->bwall;
     a.bio = c->bio;
@@ -289,6 +301,13 @@ StepArgs step_args(const lbm_ctx* c, int parity) {
     a.iop = c->iop;
     a.kinv = c->kinv;
     a.clock = c->clock;
+    a.wf_cur = c->wf_cur;
+    a.wf_firr = c->wf_firr;
+    a.wf_smask = c->wf_smask;
+    a.wf_imask = c->wf_imask;
+    a.stretch = c->stretch;
+    a.irr = c->irr;
+    a.n_irr_pad = c->n_irr_pad;
     return a;
 }
 
@@ -368,7 +387,7 @@ int init_instance(lbm_ctx* c, int inst, const double* rho, const double* u, cons
     const int64_t n = g.n;
     InitArgs a;
     a.A = c->buf[c->step & 1];
-    a.nbr = nbr_ptr(c);
+    a.nbr = nbr_rd(c);
     a.np = c->np;
     a.first = (int32_t)g.offset;
     a.n = (int32_t)n;
@@ -395,7 +414,7 @@ int init_instance(lbm_ctx* c, int inst, const double* rho, const double* u, cons
             a.u = s + n;
         }
     }
-    hipError_t e = launch_init(c->dtype, c->ibits, a, c->stream);
+    hipError_t e = launch_init(c->dtype, 32, a, c->stream);
     if (e != hipSuccess) return fail(c, LBM_EDEVICE, "init launch failed: %s", hipGetErrorString(e));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return LBM_OK;
@@ -421,7 +440,7 @@ int lbm_plan_export(const lbm_instance_desc* inst, int n_inst, const int* wall_m
     build_boundary(p, m, so, io, bl);
     if (counts) {
         counts[0] = p.N;
-        counts[1] = (int64_t)bl.site.size();
+        counts[1] = (int64_t)bl.ghost.size();
         counts[2] = (int64_t)p.wall_site.size();
         counts[3] = p.n_wall_links;
         counts[4] = p.n_iolet_links;
@@ -432,10 +451,11 @@ int lbm_plan_export(const lbm_instance_desc* inst, int n_inst, const int* wall_m
         build_device_nbr<int32_t>(p, m, p.N, t);
         std::memcpy(nbr, t.data(), t.size() * 4);
     }
-    if (boundary) std::memcpy(boundary, bl.site.data(), bl.site.size() * 4);
-    if (bmask)
-        for (size_t j = 0; j < bl.site.size(); ++j)
-            bmask[j] = (bl.wall[j] & 0x7FFFEu) | (bl.io[j] & 0x7FFFEu);
+    for (size_t j = 0; j < bl.ghost.size(); ++j) {
+        const int32_t id = bl.ghost[j];
+        if (boundary) boundary[j] = bl.site[id];
+        if (bmask) bmask[j] = (bl.wall[id] & 0x7FFFEu) | (bl.io[id] & 0x7FFFEu);
+    }
     return LBM_OK;
 }
 
@@ -479,7 +499,7 @@ int lbm_create_geometry(lbm_ctx** out, const lbm_instance_desc* inst, int n_inst
         return fail(nullptr, LBM_EINVAL, "too many iolets (%d) in one context", io);
     }
     c->have16 = c->plan.max_abs_offset <= Sentinel<int16_t>::MAXABS - 1;
-    c->ibits = c->have16 ? 16 : 32;
+    c->ibits = 0;  // compressed addressing by default
     hipError_t he = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
     if (he != hipSuccess) {
         delete c;
@@ -490,7 +510,35 @@ int lbm_create_geometry(lbm_ctx** out, const lbm_instance_desc* inst, int n_inst
     rc = rc ? rc : dalloc(c, &c->buf[0], pop_bytes);
     rc = rc ? rc : dalloc(c, &c->buf[1], pop_bytes);
     rc = rc ? rc : dalloc(c, &c->nbr32, (size_t)18 * c->np * 4);
-    rc = rc ? rc : dalloc(c, (void**)&c->bidx, (size_t)c->plan.N * 4);
+    if (!rc) {
+        // sizes of the boundary records and of the compressed addressing do
+        // not depend on the wall modes; build once to size the buffers
+        const std::vector<int> m0(n_inst, LBM_WALL_BOUNCEBACK);
+        std::vector<int32_t> t32;
+        build_device_nbr<int32_t>(c->plan, m0, c->np, t32);
+        BoundaryList bl;
+        build_boundary(c->plan, m0, c->seg_off, c->iolet_off, bl);
+        Compressed cm;
+        std::string ce = build_compressed(c->plan, bl, t32, c->np, cm);
+        if (!ce.empty()) rc = fail(c, LBM_EINVAL, "%s", ce.c_str());
+        c->n_irr = (int64_t)bl.site.size();
+        c->n_irr_pad = cm.n_irr_pad;
+        c->n_stretch = cm.n_stretch;
+        const int64_t ni = c->n_irr, nwf = c->np / 64;
+        rc = rc ? rc : dalloc(c, (void**)&c->bj, ni * 4);
+        rc = rc ? rc : dalloc(c, (void**)&c->rsite, ni * 4);
+        rc = rc ? rc : dalloc(c, (void**)&c->bidx, c->plan.N * 4);
+        rc = rc ? rc : dalloc(c, (void**)&c->bwall, ni * 4);
+        rc = rc ? rc : dalloc(c, (void**)&c->bio, ni * 4);
+        rc = rc ? rc : dalloc(c, (void**)&c->bk, ni * 4);
+        rc = rc ? rc : dalloc(c, (void**)&c->bw, ni * 4);
+        rc = rc ? rc : dalloc(c, (void**)&c->wf_cur, nwf * 4);
+        rc = rc ? rc : dalloc(c, (void**)&c->wf_firr, nwf * 4);
+        rc = rc ? rc : dalloc(c, (void**)&c->wf_smask, nwf * 8);
+        rc = rc ? rc : dalloc(c, (void**)&c->wf_imask, nwf * 8);
+        rc = rc ? rc : dalloc(c, (void**)&c->stretch, cm.stretch.size() * 4);
+        rc = rc ? rc : dalloc(c, (void**)&c->irr, cm.irr.size() * 4);
+    }
     if (c->have16) rc = rc ? rc : dalloc(c, &c->nbr16, (size_t)18 * c->np * 2);
     const int64_t nw = (int64_t)c->plan.wall_site.size();
     rc = rc ? rc : dalloc(c, (void**)&c->wsite, nw * 4);
@@ -685,8 +733,8 @@ int lbm_read_fields(lbm_ctx* c, int inst, double* rho, double* u, double* wss, f
     double* s_wss = s_u + 3 * n;
     float* s_dr = (float*)(s_wss + n);
     const void* A = c->buf[c->step & 1];
-    FieldArgs fa{A, nbr_ptr(c), c->np, (int32_t)g.offset, (int32_t)n, 1.0 / c->tau, s_rho, s_u};
-    hipError_t e = launch_fields(c->dtype, c->ibits, fa, c->stream);
+    FieldArgs fa{A, nbr_rd(c), c->np, (int32_t)g.offset, (int32_t)n, 1.0 / c->tau, s_rho, s_u};
+    hipError_t e = launch_fields(c->dtype, 32, fa, c->stream);
     if (e != hipSuccess) return fail(c, LBM_EDEVICE, "read-out launch failed: %s", hipGetErrorString(e));
     if (wss || wall_dr) {
         HIP_TRY(c, hipMemsetAsync(s_wss, 0, (size_t)n * 8, c->stream));
@@ -694,7 +742,7 @@ int lbm_read_fields(lbm_ctx* c, int inst, double* rho, double* u, double* wss, f
         const InstState& st = c->ist[inst];
         WallArgs wa;
         wa.A = A;
-        wa.nbr = nbr_ptr(c);
+        wa.nbr = nbr_rd(c);
         wa.np = c->np;
         wa.first = (int32_t)g.offset;
         wa.nw = (int32_t)(g.wall_end - g.wall_begin);
@@ -708,7 +756,7 @@ int lbm_read_fields(lbm_ctx* c, int inst, double* rho, double* u, double* wss, f
         wa.kinv = c->kinv;
         wa.wss = s_wss;
         wa.dr = s_dr;
-        e = launch_wall(c->dtype, c->ibits, wa, c->stream);
+        e = launch_wall(c->dtype, 32, wa, c->stream);
         if (e != hipSuccess) return fail(c, LBM_EDEVICE, "wall read-out launch failed: %s", hipGetErrorString(e));
     }
     std::vector<double> hr, hu;
@@ -738,9 +786,9 @@ int lbm_read_populations(lbm_ctx* c, int inst, double* f) {
     const InstanceGeom& g = c->plan.inst[inst];
     rc = ensure_scratch(c, (size_t)g.n * Q * 8);
     if (rc) return rc;
-    PopArgs a{c->buf[c->step & 1], nbr_ptr(c), c->np, (int32_t)g.offset, (int32_t)g.n,
+    PopArgs a{c->buf[c->step & 1], nbr_rd(c), c->np, (int32_t)g.offset, (int32_t)g.n,
               (double*)c->scratch.p};
-    hipError_t e = launch_read_pop(c->dtype, c->ibits, a, c->stream);
+    hipError_t e = launch_read_pop(c->dtype, 32, a, c->stream);
     if (e != hipSuccess) return fail(c, LBM_EDEVICE, "launch failed: %s", hipGetErrorString(e));
     HIP_TRY(c, hipMemcpyAsync(f, c->scratch.p, (size_t)g.n * Q * 8, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -768,9 +816,9 @@ int lbm_cycle_delta(lbm_ctx* c, int inst, double* delta_u, double* delta_p) {
     }
     hipError_t e = launch_zero_u32(c->maxes, 4, c->stream);
     if (e != hipSuccess) return fail(c, LBM_EDEVICE, "launch failed: %s", hipGetErrorString(e));
-    DeltaArgs a{c->buf[c->step & 1], nbr_ptr(c), c->np, (int32_t)g.offset, (int32_t)g.n,
+    DeltaArgs a{c->buf[c->step & 1], nbr_rd(c), c->np, (int32_t)g.offset, (int32_t)g.n,
                 1.0 / 3.0 - st.P0, (float*)st.snap.p, st.has_snap ? 1 : 0, c->maxes};
-    e = launch_delta(c->dtype, c->ibits, a, c->stream);
+    e = launch_delta(c->dtype, 32, a, c->stream);
     if (e != hipSuccess) return fail(c, LBM_EDEVICE, "launch failed: %s", hipGetErrorString(e));
     unsigned int m[4];
     HIP_TRY(c, hipMemcpyAsync(m, c->maxes, sizeof(m), hipMemcpyDeviceToHost, c->stream));
@@ -806,8 +854,13 @@ int lbm_get_info(const lbm_ctx* c, lbm_info* info) {
     info->boundary_fused = c->fused;
     info->bytes_per_site_algorithmic = 2.0 * Q * (double)c->esize;
     const double N = (double)std::max<int64_t>(1, c->plan.N);
-    info->bytes_per_site_model = 2.0 * Q * (double)c->esize + 18.0 * (c->ibits / 8) +
-                                 (double)c->nb / N * (20.0 + 18.0 * (c->ibits / 8));
+    if (c->ibits == 0)
+        info->bytes_per_site_model = 2.0 * Q * (double)c->esize + 24.0 / 64.0 +
+                                     32.0 * (double)c->n_stretch / N +
+                                     (double)c->n_irr / N * (72.0 + 20.0);
+    else
+        info->bytes_per_site_model = 2.0 * Q * (double)c->esize + 18.0 * (c->ibits / 8) +
+                                     (double)c->nb / N * 24.0;
     info->device_bytes = c->device_bytes;
     return LBM_OK;
 }
@@ -825,8 +878,8 @@ int lbm_set_launch(lbm_ctx* c, int block_size, int index_bits, int use_graph, in
     if (block_size != -1 && block_size != 64 && block_size != 128 && block_size != 256 &&
         block_size != 512 && block_size != 1024)
         return fail(c, LBM_EINVAL, "block size %d not supported", block_size);
-    if (index_bits != -1 && index_bits != 16 && index_bits != 32)
-        return fail(c, LBM_EINVAL, "index_bits must be 16 or 32");
+    if (index_bits != -1 && index_bits != 0 && index_bits != 16 && index_bits != 32)
+        return fail(c, LBM_EINVAL, "index_bits must be 0 (compressed), 16 or 32");
     if (index_bits == 16 && !c->have16)
         return fail(c, LBM_EINVAL, "a neighbour offset exceeds the 16-bit range (max %lld)",
                     (long long)c->plan.max_abs_offset);
@@ -872,7 +925,7 @@ int lbm_autotune(lbm_ctx* c, int steps_per_trial, double* best_rate) {
     TuneVal best{old_block, old_ibits, old_xcd, old_nt, old_fused};
     double best_ms = std::numeric_limits<double>::infinity();
     const int blocks[] = {128, 256, 512, 1024};
-    const int ibits_list[] = {16, 32};
+    const int ibits_list[] = {0, 16, 32};
     for (int ib : ibits_list) {
         if (ib == 16 && !c->have16) continue;
         for (int fu = 0; fu < 2 && !rc; ++fu)

@@ -81,16 +81,18 @@ def test_pulsatile_elastic_tube(dtype, fused):
         assert e["u"] <= bound and e["p"] <= bound
 
 
+@pytest.mark.parametrize("addr", [0, 32])
 @pytest.mark.parametrize("fused", [1, 0])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("seed", [1, 2])
-def test_random_boxes_every_link_type(dtype, seed, fused):
+def test_random_boxes_every_link_type(dtype, seed, fused, addr):
     """Random labels (walls, two iolets, thin gaps, opposite wall pairs),
-    three stiffness segments, random initial state, 60 steps."""
+    three stiffness segments, random initial state, 60 steps; compressed and
+    32-bit table addressing, fused and compacted boundary modes."""
     p = H.random_box_problem(seed)
-    g, r = run_pair(p, dtype, 60, launch=dict(boundary_fused=fused))
+    g, r = run_pair(p, dtype, 60, launch=dict(boundary_fused=fused, index_bits=addr))
     e = H.errors(g, r, P0=p.P0)
-    record(f"random_box_{seed}", e, dtype=dtype, steps=60, fused=fused)
+    record(f"random_box_{seed}", e, dtype=dtype, steps=60, fused=fused, addr=addr)
     tol = TOL[dtype]
     assert e["u"] <= 10 * tol and e["p"] <= tol and e["wss"] <= 100 * tol
 
@@ -140,14 +142,17 @@ def test_single_site_instances():
 
 @pytest.mark.parametrize("fused", [1, 0])
 def test_launch_configurations_are_bit_identical(fused):
-    """Block size, index width, graph replay, XCD remapping and non-temporal
-    stores change only the schedule, never the arithmetic."""
+    """Block size, addressing (compressed, 16- or 32-bit table), graph replay,
+    XCD remapping and non-temporal stores change only the schedule, never
+    the arithmetic."""
     p = H.tube_problem(10, 40, seed=6)
     ref = None
     for cfg in [dict(block_size=256, index_bits=32, use_graph=0, xcd_remap=0, nontemporal=0),
                 dict(block_size=64, index_bits=16, use_graph=1, xcd_remap=1, nontemporal=1),
                 dict(block_size=1024, index_bits=16, use_graph=1, xcd_remap=0, nontemporal=0),
-                dict(block_size=512, index_bits=32, use_graph=1, xcd_remap=1, nontemporal=1)]:
+                dict(block_size=512, index_bits=32, use_graph=1, xcd_remap=1, nontemporal=1),
+                dict(block_size=128, index_bits=0, use_graph=1, xcd_remap=1, nontemporal=0),
+                dict(block_size=1024, index_bits=0, use_graph=0, xcd_remap=0, nontemporal=1)]:
         lat = H.make_lattice([p], "f32")
         lat.set_launch(boundary_fused=fused, **cfg)
         lat.step(300)
