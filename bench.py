@@ -60,9 +60,11 @@ def traffic_from_profiles(dtype):
 
 
 def copy_probe(gib=1.0, reps=20):
-    """Achievable HBM bandwidth of a plain device copy (torch) of known size;
-    under rocprofv3 --pmc it also gives the FETCH_SIZE / WRITE_SIZE scale."""
+    """Achievable HBM bandwidth of plain device copies of known size: torch's
+    copy and the library's streaming copy (normal and non-temporal); under
+    rocprofv3 --pmc they also give the FETCH_SIZE / WRITE_SIZE scale."""
     import torch
+    from paper_2108_08783_amd import lbm
     n = int(gib * (1 << 30)) // 4
     a = torch.ones(n, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
@@ -76,7 +78,15 @@ def copy_probe(gib=1.0, reps=20):
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / reps
-    return dict(bytes_per_copy=2 * 4 * n, us=ms * 1e3, gbs=2 * 4 * n / (ms * 1e-3) / 1e9)
+    nbytes = 2 * 4 * n
+    out = dict(bytes_per_copy=nbytes, torch_us=round(ms * 1e3, 2),
+               torch_gbs=round(nbytes / (ms * 1e-3) / 1e9, 1))
+    s = torch.cuda.current_stream().cuda_stream
+    for nt in (0, 1):
+        ms = lbm.lbm_copy_probe(b.data_ptr(), a.data_ptr(), 4 * n, nontemporal=nt, reps=reps,
+                                stream=s)
+        out[f"lib{'_nt' if nt else ''}_gbs"] = round(nbytes / (ms * 1e-3) / 1e9, 1)
+    return out
 
 
 def gpu_run(wl, dtype, steps, warmup, bounceback=False, tune=True, launch=None):
@@ -89,7 +99,7 @@ def gpu_run(wl, dtype, steps, warmup, bounceback=False, tune=True, launch=None):
     if launch:
         lat.set_launch(**launch)
     elif tune:
-        lat.autotune(128)
+        lat.autotune(256)
     lat.step(warmup)
     lat.sync()
     torch.cuda.synchronize()
@@ -142,8 +152,8 @@ def cpu_baseline(wl, target_s=15.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=4000)
-    ap.add_argument("--warmup", type=int, default=256)
+    ap.add_argument("--steps", type=int, default=4096)
+    ap.add_argument("--warmup", type=int, default=512)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--dtype", default="f32")
@@ -221,7 +231,7 @@ def main():
                     index_bits=info["index_bits"], block=info["block_size"],
                     xcd_remap=info["xcd_remap"], nontemporal=info["nontemporal"],
                     boundary_fused=info["boundary_fused"],
-                    graph_steps=128, parallelism="single GPU"),
+                    graph_steps=128, parallelism="single GPU", autotune_trial_steps=256),
         roofline=roofline,
         cpu_baseline=cpu,
         secondary=secondary,

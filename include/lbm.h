@@ -108,12 +108,14 @@ typedef struct {
     int64_t step;            /* steps enqueued since creation                */
     int32_t n_instances;
     int32_t dtype;           /* enum lbm_dtype                               */
-    int32_t index_bits;      /* 16 or 32: width of the neighbour table       */
+    int32_t index_bits;      /* 0 compressed addressing, 16/32 offset table  */
     int32_t block_size;      /* threads per block of the update kernel       */
     int32_t use_graph;       /* 1: lbm_step replays captured HIP graphs      */
     int32_t xcd_remap;       /* 1: block -> XCD-contiguous site ranges       */
-    int32_t nontemporal;     /* 1: population stores bypass the caches       */
+    int32_t nontemporal;     /* bit 0 stores, bit 1 loads bypass the caches  */
     int32_t boundary_fused;  /* 1: boundary links applied inside the update   */
+    int32_t sites_per_lane;  /* sites updated per lane in the update blocks   */
+    int32_t reserved;
     double bytes_per_site_algorithmic; /* 2 * 19 * sizeof(stored type)       */
     double bytes_per_site_model;       /* + neighbour table + boundary data  */
     int64_t device_bytes;    /* device memory held by the context            */
@@ -230,21 +232,38 @@ int lbm_get_info(const lbm_ctx* ctx, lbm_info* info);
 int lbm_instance_sites(const lbm_ctx* ctx, int inst, int64_t* n);
 
 /* Launch configuration of the update kernel.  block_size in {64, 128, 256,
- * 512, 1024}; index_bits 16 or 32 (16 only if every neighbour offset fits,
- * else LBM_EINVAL); use_graph, xcd_remap, nontemporal booleans;
+ * 512, 1024}; index_bits: 0 for compressed addressing (interior sites derive
+ * their offsets from per-row offsets shared along runs of interior sites),
+ * 16 or 32 for a per-site offset table (16 only if every neighbour offset
+ * fits, else LBM_EINVAL); use_graph, xcd_remap booleans; nontemporal bit 0:
+ * population stores bypass the caches, bit 1: population loads do;
  * boundary_fused 1: sites with elastic-wall or iolet links are updated by
  * the same blocks as all other sites, which apply the link rules in place;
  * 0: they are skipped there and updated by a compacted list of boundary
  * sites in blocks appended to the same launch.  Both modes compute the same
- * link rule.  A value of -1 keeps the current setting. */
+ * link rule.  sites_per_lane: 1 (the only value this build accepts; two
+ * sites per lane measured slower on gfx950).  A value of -1 keeps the
+ * current setting.  No setting changes the arithmetic. */
 int lbm_set_launch(lbm_ctx* ctx, int block_size, int index_bits, int use_graph, int xcd_remap,
-                   int nontemporal, int boundary_fused);
+                   int nontemporal, int boundary_fused, int sites_per_lane);
 
 /* Times every launch configuration on the context's own state for
  * steps_per_trial steps each (the populations are saved and restored), keeps
  * the fastest and writes its steps per second in *best_rate (may be NULL).
  * Results are cached in-process per (sites, boundary sites, dtype). */
 int lbm_autotune(lbm_ctx* ctx, int steps_per_trial, double* best_rate);
+
+/* ---- diagnostics ----------------------------------------------------------- */
+
+/* Plain streaming device copy of `bytes` (a multiple of 16) from src to dst
+ * (caller-owned device buffers, 16-byte aligned), `reps` times on `stream`
+ * (hipStream_t, NULL = default), with 16-byte vector loads and stores,
+ * optionally non-temporal.  Writes the average milliseconds per copy.  Used
+ * as the reference for achievable HBM bandwidth and for scaling the
+ * FETCH_SIZE / WRITE_SIZE counters; not part of the method.  Errors:
+ * LBM_EINVAL, LBM_EDEVICE. */
+int lbm_copy_probe(void* dst, const void* src, size_t bytes, int nontemporal, int reps,
+                   void* stream, double* ms);
 
 /* ---- host-only geometry plan (no device needed) -------------------------- */
 

@@ -12,6 +12,7 @@
 // Sec. 3).  Every slot is read by exactly one site per step.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "../../include/lbm.h"
@@ -96,6 +97,47 @@ __device__ __forceinline__ void gather(const typename Codec<DT>::raw* __restrict
     }
 }
 
+// Byte offset of element e of a population buffer.  When every buffer is
+// smaller than 2^31 bytes (SMALL) the offset is formed in 32 bits, so the
+// load or store takes a uniform base address and a 32-bit per-lane offset.
+template <int DT, bool SMALL>
+struct Off {
+    using raw = typename Codec<DT>::raw;
+    using type = typename std::conditional<SMALL, uint32_t, uint64_t>::type;
+    __device__ static type of(int64_t e) { return (type)e * (type)sizeof(raw); }
+    __device__ static const raw* ptr(const raw* base, type off) {
+        return (const raw*)((const char*)base + off);
+    }
+    __device__ static raw* ptr(raw* base, type off) { return (raw*)((char*)base + off); }
+};
+
+template <typename raw, bool NTL>
+__device__ __forceinline__ raw ld(const raw* p) {
+    if constexpr (NTL)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
+}
+
+// NTL: non-temporal loads (every population is read exactly once per step).
+template <int DT, bool SMALL, bool NTL>
+__device__ __forceinline__ void gather32(const typename Codec<DT>::raw* __restrict__ A, int64_t np,
+                                         int x, const int32_t (&d)[18],
+                                         typename Codec<DT>::acc (&h)[Q]) {
+    using O = Off<DT, SMALL>;
+    using T = typename O::type;
+    using raw = typename O::raw;
+    const T npt = (T)np, xt = (T)x;
+    h[0] = Codec<DT>::dec(ld<raw, NTL>(O::ptr(A, xt * (T)sizeof(raw))));
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const int32_t di = d[i - 1];
+        const bool redirect = di <= Sentinel<int32_t>::GHOST;
+        const T e = redirect ? (T)dopp(i) * npt + xt : (T)i * npt + (T)(x + di);
+        h[i] = Codec<DT>::dec(ld<raw, NTL>(O::ptr(A, e * (T)sizeof(raw))));
+    }
+}
+
 // Slot of the 8-entry stretch table holding the row (y - cy, z - cz) of
 // direction i (rows in the order (1,0),(-1,0),(0,1),(0,-1),(1,1),(-1,-1),
 // (1,-1),(-1,1) of (dy,dz)); -1 for the same row.
@@ -113,10 +155,13 @@ __device__ __forceinline__ constexpr int row_slot(int i) {
 // Neighbour offsets of site x (32-bit, table sentinels) and its boundary
 // record id (-1 for interior sites; only looked up by sites with
 // boundary-pass links in table addressing).
-template <int ADDR>
+template <int ADDR, bool ALIGNED>
 __device__ __forceinline__ void site_offsets(const StepArgs& a, int x, int32_t (&d)[18], int& rec) {
     if constexpr (ADDR == ADDR_COMP) {
-        const int w = x >> 6, l = x & 63;
+        // ALIGNED: the 64 lanes of the wavefront hold the 64 sites of one
+        // record, so the record index is uniform (scalar loads)
+        const int w = ALIGNED ? __builtin_amdgcn_readfirstlane(x >> 6) : (x >> 6);
+        const int l = x & 63;
         const uint64_t im = a.wf_imask[w];
         if ((im >> l) & 1ull) {
             const int id = a.wf_firr[w] + __popcll(im & ((1ull << l) - 1ull));
@@ -243,8 +288,8 @@ __device__ __forceinline__ int remap_xcd(int b, int nblk) {
 }
 
 // Links whose upstream voxel is an elastic wall or an iolet (boundary record
-// j of a site with moments m, equilibrium deviations e and post-collision
-// deviations hs): for each such link i the value
+// j of a site with moments m and post-collision deviations out): for each
+// such link i the value
 //   f_i(x, t+1) = feq_i(rho', U') + (1 - 1/tau) (f_i - feq_i(rho, u))
 //              = feq_i(rho', U') + f*_i - feq_i(rho, u)
 // replaces out[opp(i)], the slot the site pulls for link i at the next step.
@@ -255,7 +300,6 @@ __device__ __forceinline__ int remap_xcd(int b, int nblk) {
 //   velocity iolet (Sec. 3): rho' = rho, U' = weight(x) u_io(t) dir.
 template <typename acc>
 __device__ __forceinline__ void apply_links(const StepArgs& a, int j, const Mom<acc>& m,
-                                            const acc (&e)[Q], const acc (&hs)[Q],
                                             acc (&out)[Q]) {
     const uint32_t bw = a.bwall[j], bi = a.bio[j];
     const uint32_t wmask = bw & 0x7FFFEu, imask = bi & 0x7FFFEu;
@@ -267,7 +311,6 @@ __device__ __forceinline__ void apply_links(const StepArgs& a, int j, const Mom<
         dE = dE > (acc)0 ? dE : (acc)0;
         s = ((acc)P.F + dE) / ((acc)1 + dE);
     }
-    const acc wx = s * m.ux, wy = s * m.uy, wz = s * m.uz;
     acc idr = m.drho, ir = m.rho, ix = m.ux, iy = m.uy, iz = m.uz;
     if (imask) {
         const IoletParams& q = a.iop[bi >> 19];
@@ -284,15 +327,62 @@ __device__ __forceinline__ void apply_links(const StepArgs& a, int j, const Mom<
             iz = sp * (acc)q.dir[2];
         }
     }
+    // Elastic wall links: rho' = rho, U' = s u, so
+    //   feq_i(rho, s u) - feq_i(rho, u)
+    //     = w_i rho (s - 1) (3 c.u + (s + 1) (9/2 (c.u)^2 - 3/2 u.u)),
+    // and opposite directions differ only in the sign of c.u.  The value of
+    // link i goes to slot opp(i); both slots of a pair are written from the
+    // unmodified post-collision values.
+    const acc A = m.rho * (s - (acc)1), Bs = s + (acc)1;
+    const acc u2 = (acc)1.5 * (m.ux * m.ux + m.uy * m.uy + m.uz * m.uz);
+    const acc cu[9] = {m.ux, m.uy, m.uz, m.ux + m.uy, m.ux - m.uy, m.ux + m.uz, m.ux - m.uz,
+                       m.uy + m.uz, m.uy - m.uz};
 #pragma unroll
-    for (int i = 1; i < Q; ++i) {
-        const bool isw = (wmask >> i) & 1u, isi = (imask >> i) & 1u;
-        if (isw | isi) {
-            const acc pdr = isi ? idr : m.drho, pr = isi ? ir : m.rho;
-            const acc px = isi ? ix : wx, py = isi ? iy : wy, pz = isi ? iz : wz;
-            out[dopp(i)] = heq_one<acc>(i, pdr, pr, px, py, pz) + hs[i] - e[i];
+    for (int k = 0; k < 9; ++k) {
+        const int i = 2 * k + 1, o = i + 1;
+        const bool wi = (wmask >> i) & 1u, wo = (wmask >> o) & 1u;
+        const bool ii = (imask >> i) & 1u, io = (imask >> o) & 1u;
+        const acc oi = out[i], oo = out[o];
+        const acc w = k < 3 ? W<acc>::w1 : W<acc>::w2;
+        const acc t = Bs * ((acc)4.5 * cu[k] * cu[k] - u2), p = (acc)3 * cu[k];
+        if (wi) out[o] = oi + w * A * (t + p);
+        if (wo) out[i] = oo + w * A * (t - p);
+        if (ii | io) {  // iolet links (rare): general form
+            if (ii)
+                out[o] = oi + heq_one<acc>(i, idr, ir, ix, iy, iz) -
+                         heq_one<acc>(i, m.drho, m.rho, m.ux, m.uy, m.uz);
+            if (io)
+                out[i] = oo + heq_one<acc>(o, idr, ir, ix, iy, iz) -
+                         heq_one<acc>(o, m.drho, m.rho, m.ux, m.uy, m.uz);
         }
     }
+}
+
+// Collision and store of one site whose pre-collision deviations h are
+// gathered (moments, BGK, link rules, 19 coalesced stores).
+template <int DT, bool SMALL>
+__device__ __forceinline__ void collide_store(const StepArgs& a, int x, bool ghost, int rec,
+                                              typename Codec<DT>::acc (&h)[Q]) {
+    using raw = typename Codec<DT>::raw;
+    using acc = typename Codec<DT>::acc;
+    raw* __restrict__ B = (raw*)a.B;
+    const Mom<acc> m = moments(h);
+    {
+        acc e[Q];
+        heq(m.drho, m.rho, m.ux, m.uy, m.uz, e);
+        const acc om = (acc)a.omega;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) h[i] = h[i] + om * (e[i] - h[i]);
+    }
+    acc (&out)[Q] = h;
+    if (ghost) apply_links<acc>(a, rec, m, out);
+    const bool nt = (a.nontemporal & 1) != 0;
+    using O = Off<DT, SMALL>;
+    using T = typename O::type;
+    const T npt = (T)a.np, xt = (T)x;
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+        put(O::ptr(B, ((T)i * npt + xt) * (T)sizeof(raw)), Codec<DT>::enc(out[i]), nt);
 }
 
 // One site: pull, BGK collision (Sec. 2.1 eq. LBE_SRT) and store.  A site
@@ -300,49 +390,31 @@ __device__ __forceinline__ void apply_links(const StepArgs& a, int j, const Mom<
 // the update blocks: the boundary blocks update it) or applies the link
 // rules of its boundary record in place (fused mode, and the boundary
 // blocks of the compacted mode).
-template <int DT, int ADDR>
+template <int DT, int ADDR, bool ALIGNED, bool SMALL, bool NTL>
 __device__ __forceinline__ void update_site(const StepArgs& a, int x, bool from_boundary_blocks) {
-    using raw = typename Codec<DT>::raw;
     using acc = typename Codec<DT>::acc;
-    const raw* __restrict__ A = (const raw*)a.A;
-    raw* __restrict__ B = (raw*)a.B;
     int32_t d[18];
     int rec;
-    site_offsets<ADDR>(a, x, d, rec);
+    site_offsets<ADDR, ALIGNED>(a, x, d, rec);
     bool ghost = false;
 #pragma unroll
     for (int i = 0; i < 18; ++i) ghost |= (d[i] == Sentinel<int32_t>::GHOST);
     if (ghost && !from_boundary_blocks && !a.fused) return;
     acc h[Q];
-    gather<DT, int32_t>(A, a.np, x, d, h);
-    const Mom<acc> m = moments(h);
-    acc e[Q];
-    heq(m.drho, m.rho, m.ux, m.uy, m.uz, e);
-    const acc om = (acc)a.omega;
-    acc out[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) out[i] = h[i] + om * (e[i] - h[i]);
-    if (ghost) {
-        const acc hs[Q] = {out[0], out[1], out[2], out[3], out[4], out[5], out[6],
-                           out[7], out[8], out[9], out[10], out[11], out[12],
-                           out[13], out[14], out[15], out[16], out[17], out[18]};
-        apply_links<acc>(a, rec, m, e, hs, out);
-    }
-    const bool nt = a.nontemporal != 0;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) put(B + (int64_t)i * a.np + x, Codec<DT>::enc(out[i]), nt);
+    gather32<DT, SMALL, NTL>((const typename Codec<DT>::raw*)a.A, a.np, x, d, h);
+    collide_store<DT, SMALL>(a, x, ghost, rec, h);
 }
 
-template <int DT, int ADDR>
+template <int DT, int ADDR, bool SMALL, bool NTL>
 __global__ __launch_bounds__(1024) void k_step(StepArgs a) {
     const int b = blockIdx.x;
     if (b < a.n_int_blocks) {
         const int lb = a.xcd_remap ? remap_xcd(b, a.n_int_blocks) : b;
         const int x = lb * (int)blockDim.x + (int)threadIdx.x;
-        if (x < a.n) update_site<DT, ADDR>(a, x, false);
+        if (x < a.n) update_site<DT, ADDR, true, SMALL, NTL>(a, x, false);
     } else {
         const int j = (b - a.n_int_blocks) * (int)blockDim.x + (int)threadIdx.x;
-        if (j < a.nb) update_site<DT, ADDR>(a, a.rsite[a.bj[j]], true);
+        if (j < a.nb) update_site<DT, ADDR, false, SMALL, NTL>(a, a.rsite[a.bj[j]], true);
     }
     if (b == 0 && threadIdx.x == 0) a.clock[a.clock_in ^ 1] = a.clock[a.clock_in] + 1;
 }
@@ -512,6 +584,19 @@ __global__ __launch_bounds__(256) void k_delta(DeltaArgs a) {
     if (t < 4) atomicMax(a.maxes + t, __float_as_uint(red[t][0]));
 }
 
+// Streaming copy (diagnostic bandwidth reference), grid-stride over 16-byte
+// vectors.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void k_copy(u32x4* __restrict__ dst, const u32x4* __restrict__ src,
+                                              int64_t n, int nt) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    if (nt)
+        __builtin_nontemporal_store(__builtin_nontemporal_load(src + e), dst + e);
+    else
+        dst[e] = src[e];
+}
+
 __global__ void k_zero_u32(unsigned int* p, int n) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k < n) p[k] = 0u;
@@ -541,8 +626,19 @@ hipError_t dispatch(int dtype, int ibits, Args&&... args) {
 
 template <int DT, int ADDR>
 hipError_t step_launch(const StepArgs& a, int block, hipStream_t s) {
-    const int nblk = a.n_int_blocks + (a.fused ? 0 : cdiv(a.nb, block));
-    hipLaunchKernelGGL((k_step<DT, ADDR>), dim3(nblk), dim3(block), 0, s, a);
+    const int nb_blocks = a.fused ? 0 : cdiv(a.nb, block);
+    // 32-bit byte offsets when a population buffer is below 2^31 bytes
+    const bool small = (int64_t)Q * a.np * (int64_t)sizeof(typename Codec<DT>::raw) < (1ll << 31);
+    const dim3 grid(a.n_int_blocks + nb_blocks);
+    const bool ntl = (a.nontemporal & 2) != 0;
+    if (small && ntl)
+        hipLaunchKernelGGL((k_step<DT, ADDR, true, true>), grid, dim3(block), 0, s, a);
+    else if (small)
+        hipLaunchKernelGGL((k_step<DT, ADDR, true, false>), grid, dim3(block), 0, s, a);
+    else if (ntl)
+        hipLaunchKernelGGL((k_step<DT, ADDR, false, true>), grid, dim3(block), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_step<DT, ADDR, false, false>), grid, dim3(block), 0, s, a);
     return hipGetLastError();
 }
 
@@ -623,6 +719,14 @@ hipError_t launch_read_pop(int dtype, int ibits, const PopArgs& a, hipStream_t s
 hipError_t launch_delta(int dtype, int ibits, const DeltaArgs& a, hipStream_t s) {
     return dispatch<DeltaL>(dtype, ibits, a, s);
 }
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, int nt, hipStream_t s) {
+    const int64_t n = (int64_t)(bytes / 16);
+    const int64_t blocks = (n + 255) / 256;   // one 16-byte vector per thread
+    if (blocks > INT32_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, s, (u32x4*)dst, (const u32x4*)src, n, nt);
+    return hipGetLastError();
+}
+
 hipError_t launch_zero_u32(unsigned int* p, int n, hipStream_t s) {
     hipLaunchKernelGGL(k_zero_u32, dim3(cdiv(n, 256)), dim3(256), 0, s, p, n);
     return hipGetLastError();

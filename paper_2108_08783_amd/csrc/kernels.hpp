@@ -37,7 +37,7 @@ struct StepArgs {
     int32_t nontemporal;
     int32_t clock_in;       // clock slot read this step; the other is written
     int32_t fused;          // 1: boundary links applied inside the update blocks
-    int32_t pad;
+    int32_t spt;            // sites per lane in the update blocks (1 or 2)
     double omega;           // 1 / tau
     const int32_t* bj;      // record ids of sites with boundary-pass links (compacted mode)
     const int32_t* rsite;   // record id -> site
@@ -131,5 +131,6 @@ hipError_t launch_init(int dtype, int ibits, const InitArgs& a, hipStream_t s);
 hipError_t launch_read_pop(int dtype, int ibits, const PopArgs& a, hipStream_t s);
 hipError_t launch_delta(int dtype, int ibits, const DeltaArgs& a, hipStream_t s);
 hipError_t launch_zero_u32(unsigned int* p, int n, hipStream_t s);
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, int nt, hipStream_t s);
 
 }  // namespace lbm

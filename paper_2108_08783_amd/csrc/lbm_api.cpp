@@ -48,7 +48,7 @@ struct TuneKey {
     }
 };
 struct TuneVal {
-    int block, ibits, xcd, nt, fused;
+    int block, ibits, xcd, nt, fused, spt;
 };
 std::mutex g_tune_mu;
 std::map<TuneKey, TuneVal> g_tune_cache;
@@ -103,7 +103,7 @@ struct lbm_ctx {
     int64_t step = 0;
     bool tables_dirty = true, params_dirty = true;
     // launch configuration
-    int block = 256, ibits = 32, use_graph = 1, xcd = 1, nt = 0, fused = 1;
+    int block = 256, ibits = 32, use_graph = 1, xcd = 1, nt = 0, fused = 1, spt = 1;
     hipStream_t stream = nullptr;
     hipGraphExec_t graph[2] = {nullptr, nullptr};  // by buffer parity at start
     int64_t device_bytes = 0;
@@ -282,13 +282,13 @@ StepArgs step_args(const lbm_ctx* c, int parity) {
     a.nbr = nbr_ptr(c);
     a.np = c->np;
     a.n = (int32_t)c->plan.N;
-    a.n_int_blocks = (int32_t)((c->plan.N + c->block - 1) / c->block);
+    a.n_int_blocks = (int32_t)((c->plan.N + (int64_t)c->block * c->spt - 1) / ((int64_t)c->block * c->spt));
     a.nb = (int32_t)c->nb;
     a.xcd_remap = c->xcd;
     a.nontemporal = c->nt;
     a.clock_in = parity;
     a.fused = c->fused;
-    a.pad = 0;
+    a.spt = c->spt;
     a.omega = 1.0 / c->tau;
     a.bj = c->bj;
     a.rsite = c->rsite;
@@ -426,6 +426,28 @@ extern "C" {
 
 const char* lbm_last_error(const lbm_ctx* ctx) {
     return ctx ? ctx->err.c_str() : g_last_error.c_str();
+}
+
+int lbm_copy_probe(void* dst, const void* src, size_t bytes, int nontemporal, int reps,
+                   void* stream, double* ms) {
+    if (!dst || !src || !ms || bytes == 0 || bytes % 16 || reps < 1 ||
+        ((uintptr_t)dst | (uintptr_t)src) % 16)
+        return fail(nullptr, LBM_EINVAL, "lbm_copy_probe: bad arguments");
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    HIP_TRY(nullptr, launch_copy(dst, src, bytes, nontemporal, s));  // warm-up
+    HIP_TRY(nullptr, hipEventCreate(&e0));
+    HIP_TRY(nullptr, hipEventCreate(&e1));
+    HIP_TRY(nullptr, hipEventRecord(e0, s));
+    for (int r = 0; r < reps; ++r) HIP_TRY(nullptr, launch_copy(dst, src, bytes, nontemporal, s));
+    HIP_TRY(nullptr, hipEventRecord(e1, s));
+    HIP_TRY(nullptr, hipEventSynchronize(e1));
+    float t = 0;
+    HIP_TRY(nullptr, hipEventElapsedTime(&t, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms = t / reps;
+    return LBM_OK;
 }
 
 int lbm_plan_export(const lbm_instance_desc* inst, int n_inst, const int* wall_mode,
@@ -852,6 +874,7 @@ int lbm_get_info(const lbm_ctx* c, lbm_info* info) {
     info->xcd_remap = c->xcd;
     info->nontemporal = c->nt;
     info->boundary_fused = c->fused;
+    info->sites_per_lane = c->spt;
     info->bytes_per_site_algorithmic = 2.0 * Q * (double)c->esize;
     const double N = (double)std::max<int64_t>(1, c->plan.N);
     if (c->ibits == 0)
@@ -873,13 +896,15 @@ int lbm_instance_sites(const lbm_ctx* c, int inst, int64_t* n) {
 }
 
 int lbm_set_launch(lbm_ctx* c, int block_size, int index_bits, int use_graph, int xcd_remap,
-                   int nontemporal, int boundary_fused) {
+                   int nontemporal, int boundary_fused, int sites_per_lane) {
     if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
     if (block_size != -1 && block_size != 64 && block_size != 128 && block_size != 256 &&
         block_size != 512 && block_size != 1024)
         return fail(c, LBM_EINVAL, "block size %d not supported", block_size);
     if (index_bits != -1 && index_bits != 0 && index_bits != 16 && index_bits != 32)
         return fail(c, LBM_EINVAL, "index_bits must be 0 (compressed), 16 or 32");
+    if (sites_per_lane != -1 && sites_per_lane != 1)
+        return fail(c, LBM_EINVAL, "sites_per_lane must be 1");
     if (index_bits == 16 && !c->have16)
         return fail(c, LBM_EINVAL, "a neighbour offset exceeds the 16-bit range (max %lld)",
                     (long long)c->plan.max_abs_offset);
@@ -887,8 +912,9 @@ int lbm_set_launch(lbm_ctx* c, int block_size, int index_bits, int use_graph, in
     if (index_bits != -1) c->ibits = index_bits;
     if (use_graph != -1) c->use_graph = use_graph ? 1 : 0;
     if (xcd_remap != -1) c->xcd = xcd_remap ? 1 : 0;
-    if (nontemporal != -1) c->nt = nontemporal ? 1 : 0;
+    if (nontemporal != -1) c->nt = nontemporal & 3;
     if (boundary_fused != -1) c->fused = boundary_fused ? 1 : 0;
+    if (sites_per_lane != -1) c->spt = sites_per_lane;
     drop_graphs(c);
     return LBM_OK;
 }
@@ -904,7 +930,7 @@ int lbm_autotune(lbm_ctx* c, int steps_per_trial, double* best_rate) {
         auto it = g_tune_cache.find(key);
         if (it != g_tune_cache.end() && !best_rate) {
             const TuneVal& v = it->second;
-            return lbm_set_launch(c, v.block, v.ibits, -1, v.xcd, v.nt, v.fused);
+            return lbm_set_launch(c, v.block, v.ibits, -1, v.xcd, v.nt, v.fused, v.spt);
         }
     }
     // save the state: both buffers and the clock
@@ -921,29 +947,51 @@ int lbm_autotune(lbm_ctx* c, int steps_per_trial, double* best_rate) {
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     const int64_t step_save = c->step;
     const int old_block = c->block, old_ibits = c->ibits, old_xcd = c->xcd, old_nt = c->nt,
-              old_fused = c->fused;
-    TuneVal best{old_block, old_ibits, old_xcd, old_nt, old_fused};
+              old_fused = c->fused, old_spt = c->spt;
+    TuneVal best{old_block, old_ibits, old_xcd, old_nt, old_fused, old_spt};
     double best_ms = std::numeric_limits<double>::infinity();
     const int blocks[] = {128, 256, 512, 1024};
     const int ibits_list[] = {0, 16, 32};
+    // pass 1: every configuration once (non-temporal loads are left out:
+    // the gathers share cache lines between neighbouring wavefronts)
+    std::vector<std::pair<double, TuneVal>> cand;
     for (int ib : ibits_list) {
         if (ib == 16 && !c->have16) continue;
         for (int fu = 0; fu < 2 && !rc; ++fu)
-        for (int bs : blocks)
-            for (int xr = 0; xr < 2; ++xr)
-                for (int ntv = 0; ntv < 2; ++ntv) {
-                    rc = lbm_set_launch(c, bs, ib, -1, xr, ntv, fu);
-                    if (rc) break;
-                    double ms = 0;
-                    rc = run_steps(c, 2);  // warm-up (and graph build)
-                    rc = rc ? rc : lbm_time_steps(c, steps_per_trial, &ms);
-                    if (rc) break;
-                    if (ms < best_ms) {
-                        best_ms = ms;
-                        best = {bs, ib, xr, ntv, fu};
+            for (int bs : blocks)
+                for (int xr = 0; xr < 2 && !rc; ++xr)
+                    for (int ntv = 0; ntv < 2 && !rc; ++ntv) {
+                        rc = lbm_set_launch(c, bs, ib, -1, xr, ntv, fu, 1);
+                        if (rc) break;
+                        double ms = 0;
+                        rc = run_steps(c, 2);  // warm-up (and graph build)
+                        rc = rc ? rc : lbm_time_steps(c, steps_per_trial, &ms);
+                        if (rc) break;
+                        cand.push_back({ms, TuneVal{bs, ib, xr, ntv, fu, 1}});
                     }
-                }
         if (rc) break;
+    }
+    // pass 2: the four fastest again, twice each with twice the steps
+    if (!rc) {
+        std::sort(cand.begin(), cand.end(),
+                  [](const std::pair<double, TuneVal>& a, const std::pair<double, TuneVal>& b) {
+                      return a.first < b.first;
+                  });
+        const size_t top = std::min<size_t>(4, cand.size());
+        for (size_t k = 0; k < top && !rc; ++k) {
+            const TuneVal& v = cand[k].second;
+            rc = lbm_set_launch(c, v.block, v.ibits, -1, v.xcd, v.nt, v.fused, v.spt);
+            double t = std::numeric_limits<double>::infinity();
+            for (int r = 0; r < 2 && !rc; ++r) {
+                double ms = 0;
+                rc = lbm_time_steps(c, 2 * steps_per_trial, &ms);
+                t = std::min(t, ms / 2.0);
+            }
+            if (!rc && t < best_ms) {
+                best_ms = t;
+                best = v;
+            }
+        }
     }
     // restore
     HIP_TRY(c, hipMemcpyAsync(c->buf[0], save0, pop_bytes, hipMemcpyDeviceToDevice, c->stream));
@@ -954,10 +1002,10 @@ int lbm_autotune(lbm_ctx* c, int steps_per_trial, double* best_rate) {
     dfree(c, save1);
     c->step = step_save;
     if (rc) {
-        lbm_set_launch(c, old_block, old_ibits, -1, old_xcd, old_nt, old_fused);
+        lbm_set_launch(c, old_block, old_ibits, -1, old_xcd, old_nt, old_fused, old_spt);
         return rc;
     }
-    rc = lbm_set_launch(c, best.block, best.ibits, -1, best.xcd, best.nt, best.fused);
+    rc = lbm_set_launch(c, best.block, best.ibits, -1, best.xcd, best.nt, best.fused, best.spt);
     if (rc) return rc;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);

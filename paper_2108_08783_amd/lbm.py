@@ -30,7 +30,7 @@ EXPORTS = [
     "lbm_set_iolet", "lbm_init_fields", "lbm_init_fields_device", "lbm_step", "lbm_sync",
     "lbm_get_stream", "lbm_time_steps", "lbm_read_fields", "lbm_read_populations",
     "lbm_write_populations", "lbm_cycle_delta", "lbm_get_info", "lbm_instance_sites",
-    "lbm_set_launch", "lbm_autotune", "lbm_plan_export",
+    "lbm_set_launch", "lbm_autotune", "lbm_plan_export", "lbm_copy_probe",
 ]
 
 
@@ -58,11 +58,12 @@ class Info(ctypes.Structure):
                 ("index_bits", ctypes.c_int32), ("block_size", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
                 ("nontemporal", ctypes.c_int32), ("boundary_fused", ctypes.c_int32),
+                ("sites_per_lane", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("bytes_per_site_algorithmic", ctypes.c_double),
                 ("bytes_per_site_model", ctypes.c_double), ("device_bytes", ctypes.c_int64)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
 _lib = None
@@ -102,9 +103,10 @@ def load():
         "lbm_cycle_delta": [P, I, P, P],
         "lbm_get_info": [P, P],
         "lbm_instance_sites": [P, I, P],
-        "lbm_set_launch": [P, I, I, I, I, I, I],
+        "lbm_set_launch": [P, I, I, I, I, I, I, I],
         "lbm_autotune": [P, I, P],
         "lbm_plan_export": [P, I, P, P, P, P, P],
+        "lbm_copy_probe": [P, P, ctypes.c_size_t, I, I, P, P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -240,15 +242,24 @@ def lbm_get_info(ctx):
 
 
 def lbm_set_launch(ctx, block_size=-1, index_bits=-1, use_graph=-1, xcd_remap=-1,
-                   nontemporal=-1, boundary_fused=-1):
+                   nontemporal=-1, boundary_fused=-1, sites_per_lane=-1):
     _check(load().lbm_set_launch(ctx, block_size, index_bits, use_graph, xcd_remap, nontemporal,
-                                 boundary_fused), ctx)
+                                 boundary_fused, sites_per_lane), ctx)
 
 
 def lbm_autotune(ctx, steps_per_trial=64):
     r = ctypes.c_double()
     _check(load().lbm_autotune(ctx, int(steps_per_trial), ctypes.byref(r)), ctx)
     return r.value
+
+
+def lbm_copy_probe(dst_ptr, src_ptr, nbytes, nontemporal=False, reps=20, stream=0):
+    """Average milliseconds of a plain device copy (diagnostic)."""
+    ms = ctypes.c_double()
+    _check(load().lbm_copy_probe(ctypes.c_void_p(dst_ptr), ctypes.c_void_p(src_ptr), int(nbytes),
+                                 int(nontemporal), int(reps), ctypes.c_void_p(stream),
+                                 ctypes.byref(ms)), None)
+    return ms.value
 
 
 def lbm_plan_export(geoms, wall_modes=None, tables=True):
