@@ -405,8 +405,14 @@ __device__ __forceinline__ void update_site(const StepArgs& a, int x, bool from_
     collide_store<DT, SMALL>(a, x, ghost, rec, h);
 }
 
+// 16-bit storage is latency-bound: 8 waves per SIMD (at the cost of a few
+// spilled registers) beats 6; 32/64-bit storage keeps the compiler's choice.
+template <int DT>
+constexpr int step_waves() { return (DT == LBM_F16DEV || DT == LBM_BF16DEV) ? 8 : 1; }
+
 template <int DT, int ADDR, bool SMALL, bool NTL>
-__global__ __launch_bounds__(1024) void k_step(StepArgs a) {
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(step_waves<DT>())))
+void k_step(StepArgs a) {
     const int b = blockIdx.x;
     if (b < a.n_int_blocks) {
         const int lb = a.xcd_remap ? remap_xcd(b, a.n_int_blocks) : b;
