@@ -92,7 +92,9 @@ def copy_probe(gib=1.0, reps=20):
 def gpu_run(wl, dtype, steps, warmup, bounceback=False, tune=True, launch=None):
     import torch
     from paper_2108_08783_amd import lbm, workloads
+    tc = time.perf_counter()
     lat = workloads.lattice(wl, dtype)
+    t_create = time.perf_counter() - tc
     if bounceback:
         for k, p in enumerate(wl.params):
             lat.set_wall(k, lbm.BOUNCEBACK, F=0.0, P0=p.P0, k=p.k)
@@ -100,6 +102,7 @@ def gpu_run(wl, dtype, steps, warmup, bounceback=False, tune=True, launch=None):
         lat.set_launch(**launch)
     elif tune:
         lat.autotune(256)
+    t_tune = time.perf_counter() - tc - t_create
     lat.step(warmup)
     lat.sync()
     torch.cuda.synchronize()
@@ -112,6 +115,8 @@ def gpu_run(wl, dtype, steps, warmup, bounceback=False, tune=True, launch=None):
         lat.read_fields(k, wss=False, wall_dr=False)  # raises if diverged
     lat.close()
     n = info["n_sites"]
+    print(f"[bench]   {dtype}: create {t_create:.1f}s, tune {t_tune:.1f}s, timed {t1 - t0:.2f}s",
+          file=sys.stderr, flush=True)
     return dict(n=n, wall_s=t1 - t0, event_ms=ms, info=info,
                 mlups=n * steps / (t1 - t0) / 1e6,
                 launch_us=ms * 1e3 / steps)

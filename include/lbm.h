@@ -283,6 +283,17 @@ int lbm_copy_probe(void* dst, const void* src, size_t bytes, int nontemporal, in
 int lbm_plan_export(const lbm_instance_desc* inst, int n_inst, const int* wall_mode,
                     int64_t* counts, int32_t* nbr, int32_t* boundary, uint32_t* bmask);
 
+/* Runs the host part of the compressed neighbour addressing of the update
+ * kernel for n_inst instances (wall modes as for lbm_plan_export),
+ * including its check that the compressed form reproduces the neighbour
+ * table at every site, and writes
+ *   stats[4] = {stretches, irregular sites, exceptional sites (rows of
+ *               several fluid runs, full offsets kept), wavefront records}.
+ * No device call is made.  Errors: LBM_EINVAL (invalid geometry, NULL
+ * stats, or the check failed). */
+int lbm_plan_compressed(const lbm_instance_desc* inst, int n_inst, const int* wall_mode,
+                        int64_t* stats);
+
 #ifdef __cplusplus
 }
 #endif

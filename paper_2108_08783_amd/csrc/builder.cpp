@@ -163,74 +163,187 @@ void build_boundary(const Plan& plan, const std::vector<int>& mode,
     }
 }
 
+namespace {
+
+// Stretch slot of direction i's upstream row (y - cy, z - cz); -1 for the
+// site's own row.
+int row_of(int i) {
+    if (CY[i] == 0 && CZ[i] == 0) return -1;
+    for (int r = 0; r < 8; ++r)
+        if (ROW8[r][0] == -CY[i] && ROW8[r][1] == -CZ[i]) return r;
+    return -1;
+}
+
+bool is_sentinel(int32_t v) { return v <= Sentinel<int32_t>::GHOST; }
+
+}  // namespace
+
 std::string build_compressed(const Plan& plan, const BoundaryList& bl,
                              const std::vector<int32_t>& nbr_dev32, int64_t n_pad, Compressed& out) {
     out = Compressed();
     const int64_t N = plan.N;
     const int64_t nwf = n_pad / 64;
-    out.wf_cur.assign(nwf, -1);
-    out.wf_firr.assign(nwf, 0);
-    out.wf_smask.assign(nwf, 0);
-    out.wf_imask.assign(nwf, 0);
+    int rowi[Q];
+    for (int i = 0; i < Q; ++i) rowi[i] = row_of(i);
+    auto tab = [&](int i, int64_t x) { return nbr_dev32[(size_t)(i - 1) * n_pad + x]; };
+
+    // pass 1: row constraints of every site; exceptional sites
     out.n_irr = (int64_t)bl.site.size();
-    out.n_irr_pad = (out.n_irr + 255) / 256 * 256;
-    out.irr.assign((size_t)18 * std::max<int64_t>(out.n_irr_pad, 256), 0);
+    out.nfm.assign((size_t)std::max<int64_t>(out.n_irr, 1), 0u);
+    std::vector<int32_t> exc_sites;
+    std::vector<uint8_t> exceptional(N, 0);
     for (int64_t j = 0; j < out.n_irr; ++j) {
-        const int32_t x = bl.site[j];
-        for (int i = 0; i < 18; ++i) out.irr[(size_t)i * out.n_irr_pad + j] = nbr_dev32[(size_t)i * n_pad + x];
+        const int64_t x = bl.site[j];
+        uint32_t m = 0;
+        bool ghost = false, bad = false;
+        int32_t C[8];
+        bool has[8] = {false};
+        for (int i = 1; i < Q; ++i) {
+            const int32_t v = tab(i, x);
+            if (is_sentinel(v)) {
+                m |= 1u << (i - 1);
+                ghost |= v == Sentinel<int32_t>::GHOST;
+                continue;
+            }
+            const int r = rowi[i];
+            if (r < 0) {
+                bad |= v != -CX[i];
+            } else if (has[r]) {
+                bad |= C[r] != v + CX[i];
+            } else {
+                has[r] = true;
+                C[r] = v + CX[i];
+            }
+        }
+        out.nfm[j] = m | (ghost ? 1u << 31 : 0u);
+        if (bad) {
+            exceptional[x] = 1;
+            exc_sites.push_back((int32_t)x);
+        }
     }
-    int32_t cur = -1, nirr = 0;
-    bool prev_interior = false;
-    int32_t prevD[8] = {0};
+    out.n_exc = (int64_t)exc_sites.size();
+    out.n_exc_pad = std::max<int64_t>(256, (out.n_exc + 255) / 256 * 256);
+    out.exc.assign((size_t)18 * out.n_exc_pad, Sentinel<int32_t>::BB);
+    for (int64_t e = 0; e < out.n_exc; ++e)
+        for (int i = 1; i < Q; ++i) out.exc[(size_t)(i - 1) * out.n_exc_pad + e] = tab(i, exc_sites[e]);
+
+    // pass 2: stretches (greedy: a site joins the current stretch when its
+    // fluid row links agree with the entries already set) and the records
+    out.wf.assign((size_t)nwf, WfRec{});
+    int32_t cur = -1, nirr = 0, nexc = 0;
+    int32_t D[8] = {0};
+    bool known[8] = {false};
     for (int64_t w = 0; w < nwf; ++w) {
-        out.wf_cur[w] = cur;
-        out.wf_firr[w] = nirr;
-        uint64_t sm = 0, im = 0;
+        WfRec& R = out.wf[w];
+        R.cur = cur;
+        R.firr = nirr;
+        R.fexc = nexc;
+        R.pad = 0;
+        R.smask = R.imask = R.emask = R.pad2 = 0;
         for (int l = 0; l < 64; ++l) {
             const int64_t x = w * 64 + l;
             if (x >= N) break;
-            if (bl.rec_of_site[x] >= 0) {
-                im |= 1ull << l;
+            const bool irr = bl.rec_of_site[x] >= 0;
+            if (irr) {
+                R.imask |= 1ull << l;
                 ++nirr;
-                prev_interior = false;
+            }
+            if (exceptional[x]) {
+                R.emask |= 1ull << l;
+                ++nexc;
                 continue;
             }
-            int32_t D[8];
-            for (int r = 0; r < 8; ++r) {
-                // the direction whose upstream voxel is (x, y+dy, z+dz): c = (0, -dy, -dz)
-                int dir = -1;
-                for (int i = 1; i < Q; ++i)
-                    if (CX[i] == 0 && CY[i] == -ROW8[r][0] && CZ[i] == -ROW8[r][1]) dir = i;
-                D[r] = plan.nbr[(size_t)(dir - 1) * N + x];
-            }
-            // the derived offsets must reproduce the site's table exactly
+            int32_t C[8];
+            bool has[8] = {false};
             for (int i = 1; i < Q; ++i) {
-                int32_t d;
-                if (CY[i] == 0 && CZ[i] == 0) {
-                    d = -CX[i];
-                } else {
-                    int r = 0;
-                    while (!(ROW8[r][0] == -CY[i] && ROW8[r][1] == -CZ[i])) ++r;
-                    d = D[r] - CX[i];
-                }
-                if (d != plan.nbr[(size_t)(i - 1) * N + x])
-                    return "compressed addressing: derived offset mismatch at site " +
-                           std::to_string(x);
+                const int32_t v = tab(i, x);
+                if (is_sentinel(v) || rowi[i] < 0) continue;
+                has[rowi[i]] = true;
+                C[rowi[i]] = v + CX[i];
             }
-            if (!prev_interior || std::memcmp(D, prevD, sizeof(D)) != 0) {
+            bool fits = cur >= 0;
+            for (int r = 0; r < 8 && fits; ++r) fits = !has[r] || !known[r] || D[r] == C[r];
+            if (!fits) {
                 ++cur;
+                for (int r = 0; r < 8; ++r) {
+                    known[r] = has[r];
+                    D[r] = has[r] ? C[r] : 0;
+                }
                 out.stretch.insert(out.stretch.end(), D, D + 8);
-                sm |= 1ull << l;
-                std::memcpy(prevD, D, sizeof(D));
+                R.smask |= 1ull << l;
+            } else {
+                for (int r = 0; r < 8; ++r)
+                    if (has[r] && !known[r]) {
+                        known[r] = true;
+                        D[r] = C[r];
+                        out.stretch[(size_t)8 * cur + r] = C[r];
+                    }
             }
-            prev_interior = true;
         }
-        out.wf_smask[w] = sm;
-        out.wf_imask[w] = im;
     }
     out.n_stretch = cur + 1;
     if (out.stretch.empty()) out.stretch.assign(8, 0);
+    if (nirr != out.n_irr) return "compressed addressing: irregular-site count mismatch";
+
+    // check: the device's reconstruction reproduces the table at every site
+    for (int64_t x = 0; x < N; ++x) {
+        const WfRec& R = out.wf[x >> 6];
+        const int l = (int)(x & 63);
+        const uint64_t bit = 1ull << l, below = bit - 1ull;
+        int st = R.cur + __builtin_popcountll(R.smask & (bit | below));
+        st = st < 0 ? 0 : st;
+        uint32_t nf = 0;
+        if (R.imask & bit) {
+            const int64_t id = R.firr + __builtin_popcountll(R.imask & below);
+            if (bl.site[id] != x) return "compressed addressing: irregular id mismatch at site " +
+                                         std::to_string(x);
+            nf = out.nfm[id];
+        }
+        const bool exc = (R.emask & bit) != 0;
+        const int64_t eid = R.fexc + __builtin_popcountll(R.emask & below);
+        bool ghost_tab = false, ghost_rec = false;
+        for (int i = 1; i < Q; ++i) {
+            const int32_t want = tab(i, x);
+            ghost_tab |= want == Sentinel<int32_t>::GHOST;
+            int32_t got;
+            if (exc) {
+                got = out.exc[(size_t)(i - 1) * out.n_exc_pad + eid];
+            } else if ((nf >> (i - 1)) & 1u) {
+                got = (nf >> 31) ? Sentinel<int32_t>::GHOST : Sentinel<int32_t>::BB;
+            } else {
+                got = (rowi[i] < 0 ? 0 : out.stretch[(size_t)8 * st + rowi[i]]) - CX[i];
+            }
+            ghost_rec |= got == Sentinel<int32_t>::GHOST;
+            const bool ok = is_sentinel(want) ? is_sentinel(got) : got == want;
+            if (!ok)
+                return "compressed addressing: derived offset mismatch at site " + std::to_string(x);
+        }
+        if (ghost_tab != ghost_rec)
+            return "compressed addressing: boundary-link flag mismatch at site " + std::to_string(x);
+    }
     return "";
+}
+
+void refresh_compressed(const BoundaryList& bl, const std::vector<int32_t>& nbr_dev32,
+                        int64_t n_pad, Compressed& c) {
+    auto tab = [&](int i, int64_t x) { return nbr_dev32[(size_t)(i - 1) * n_pad + x]; };
+    for (int64_t j = 0; j < c.n_irr; ++j) {
+        const int64_t x = bl.site[j];
+        bool ghost = false;
+        for (int i = 1; i < Q; ++i) ghost |= tab(i, x) == Sentinel<int32_t>::GHOST;
+        c.nfm[j] = (c.nfm[j] & 0x7FFFFFFFu) | (ghost ? 1u << 31 : 0u);
+    }
+    int64_t e = 0;
+    for (const WfRec& R : c.wf) {
+        uint64_t m = R.emask;
+        const int64_t base = (int64_t)(&R - c.wf.data()) * 64;
+        while (m) {
+            const int l = __builtin_ctzll(m);
+            m &= m - 1;
+            for (int i = 1; i < Q; ++i) c.exc[(size_t)(i - 1) * c.n_exc_pad + e] = tab(i, base + l);
+            ++e;
+        }
+    }
 }
 
 template <typename I>

@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "../../include/lbm.h"
+#include "d3q19.hpp"
 
 namespace lbm {
 
@@ -63,33 +64,51 @@ void build_boundary(const Plan& plan, const std::vector<int>& mode,
                     const std::vector<int>& seg_off, const std::vector<int>& iolet_off,
                     BoundaryList& out);
 
-// Compressed addressing.  Offsets of an interior site (all 18 upstream
-// voxels fluid) follow from the 8 offsets d(dy,dz) to the voxel at the same
-// x in the neighbouring rows (y+dy, z+dz): the upstream voxel of direction
-// c is at d(-cy,-cz) - cx (x-neighbours in a row are consecutive sites).
-// Along a run of consecutive interior sites in one row these 8 offsets are
-// constant (a "stretch").  Per wavefront of 64 consecutive sites:
-//   cur    id of the stretch of the last interior site before the wavefront
+// Compressed addressing.  Offsets of a site follow from the 8 offsets
+// d(dy,dz) to the voxel at the same x in the neighbouring rows (y+dy, z+dz):
+// the upstream voxel of direction c is at d(-cy,-cz) - cx, and the
+// x-neighbours in a row are consecutive sites.  Along a row that is one run
+// of fluid voxels these 8 offsets are constant, also at the row's irregular
+// sites for the links that reach fluid (a "stretch"); a stretch may leave
+// entries unset that none of its sites uses.  Every site belongs to the
+// current stretch unless it starts a new one; an irregular site carries an
+// 18-bit mask of its non-fluid links (bit i-1 for direction i; bit 31: at
+// least one of them is handled by the boundary rule).  The rare irregular
+// sites whose fluid links disagree with any single stretch ("exceptional":
+// a row of several runs) keep all 18 offsets.  Per wavefront of 64
+// consecutive sites one record holds
+//   cur    id of the stretch in effect before the wavefront
 //   firr   id of the first irregular site at or after the wavefront start
+//   fexc   id of the first exceptional site at or after the wavefront start
 //   smask  bit l: site l starts a new stretch
 //   imask  bit l: site l is irregular
-// so stretch(l) = cur + popcount(smask & bits 0..l) and
-// irregular id(l) = firr + popcount(imask & bits 0..l-1).  Irregular sites
-// keep all 18 offsets (32-bit, with the sentinels of Sentinel<int32_t>).
+//   emask  bit l: site l is exceptional (a subset of imask)
+// so stretch(l) = cur + popcount(smask & bits 0..l), irregular id(l) =
+// firr + popcount(imask & bits 0..l-1) (also the boundary record id) and
+// exceptional id(l) = fexc + popcount(emask & bits 0..l-1).
 struct Compressed {
-    std::vector<int32_t> wf_cur, wf_firr;
-    std::vector<uint64_t> wf_smask, wf_imask;
-    std::vector<int32_t> stretch;  // 8 per stretch, (dy,dz) in order of ROW8
-    std::vector<int32_t> irr;      // 18 planes x n_irr_pad
-    int64_t n_irr = 0, n_irr_pad = 0, n_stretch = 0;
+    std::vector<WfRec> wf;
+    std::vector<int32_t> stretch;  // 8 per stretch, (dy, dz) in order of ROW8
+    std::vector<uint32_t> nfm;     // per irregular site: non-fluid link mask
+    std::vector<int32_t> exc;      // 18 planes x n_exc_pad, Sentinel<int32_t> codes
+    int64_t n_irr = 0, n_exc = 0, n_exc_pad = 0, n_stretch = 0;
 };
 
 // (dy, dz) of the 8 neighbouring rows, in stretch-table order.
 constexpr int ROW8[8][2] = {{1, 0}, {-1, 0}, {0, 1}, {0, -1}, {1, 1}, {-1, -1}, {1, -1}, {-1, 1}};
 
-// Returns an empty string on success.
+// Builds the compressed form from the device table (Sentinel<int32_t>
+// codes, n_pad sites per plane) and checks that it reproduces the table at
+// every site.  Returns an empty string on success.
 std::string build_compressed(const Plan& plan, const BoundaryList& bl,
                              const std::vector<int32_t>& nbr_dev32, int64_t n_pad, Compressed& out);
+
+// Rewrites the parts of a compressed form that depend on the wall modes
+// (the boundary-rule flag of each link mask and the sentinels of the
+// exceptional sites' offsets) from the device table of the current modes;
+// which links are non-fluid, the stretches and the records do not change.
+void refresh_compressed(const BoundaryList& bl, const std::vector<int32_t>& nbr_dev32,
+                        int64_t n_pad, Compressed& c);
 
 // Device neighbour table of width I for the given wall modes.
 template <typename I>

@@ -45,4 +45,12 @@ struct Sentinel<int16_t> {
     static constexpr int64_t MAXABS = INT16_MAX;
 };
 
+// Per-wavefront record of the compressed addressing (layout shared by the
+// host builder and the update kernel; fields described in builder.hpp).
+struct alignas(16) WfRec {
+    int32_t cur, firr, fexc, pad;
+    uint64_t smask, imask, emask, pad2;
+};
+static_assert(sizeof(WfRec) == 48, "wavefront record layout");
+
 }  // namespace lbm

@@ -159,26 +159,36 @@ template <int ADDR, bool ALIGNED>
 __device__ __forceinline__ void site_offsets(const StepArgs& a, int x, int32_t (&d)[18], int& rec) {
     if constexpr (ADDR == ADDR_COMP) {
         // ALIGNED: the 64 lanes of the wavefront hold the 64 sites of one
-        // record, so the record index is uniform (scalar loads)
+        // record, so the record is loaded with scalar loads.  The stretch
+        // (every lane) and the link mask (irregular lanes) depend only on
+        // the record and are loaded together, so the gathers wait for two
+        // memory round trips.
         const int w = ALIGNED ? __builtin_amdgcn_readfirstlane(x >> 6) : (x >> 6);
         const int l = x & 63;
-        const uint64_t im = a.wf_imask[w];
-        if ((im >> l) & 1ull) {
-            const int id = a.wf_firr[w] + __popcll(im & ((1ull << l) - 1ull));
-            rec = id;
+        const WfRec r = a.wf[w];
+        const uint64_t bit = 1ull << l, below = bit - 1ull;
+        int st = r.cur + __popcll(r.smask & (bit | below));
+        st = st < 0 ? 0 : st;
+        const int4* S = (const int4*)(a.stretch + 8 * (int64_t)st);
+        const int4 s0 = S[0], s1 = S[1];
+        uint32_t nf = 0;
+        rec = -1;
+        if (r.imask & bit) {
+            rec = r.firr + __popcll(r.imask & below);
+            nf = a.nfm[rec];
+        }
+        const int32_t D[8] = {s0.x, s0.y, s0.z, s0.w, s1.x, s1.y, s1.z, s1.w};
+        const int32_t sent = (nf >> 31) ? Sentinel<int32_t>::GHOST : Sentinel<int32_t>::BB;
 #pragma unroll
-            for (int i = 0; i < 18; ++i) d[i] = a.irr[(int64_t)i * a.n_irr_pad + id];
-        } else {
-            rec = -1;
-            const int st = a.wf_cur[w] + __popcll(a.wf_smask[w] & (~0ull >> (63 - l)));
-            const int4* S = (const int4*)(a.stretch + 8 * (int64_t)st);
-            const int4 s0 = S[0], s1 = S[1];
-            const int D[8] = {s0.x, s0.y, s0.z, s0.w, s1.x, s1.y, s1.z, s1.w};
+        for (int i = 1; i < Q; ++i) {
+            const int rs = row_slot(i);
+            d[i - 1] = ((nf >> (i - 1)) & 1u) ? sent : (rs < 0 ? 0 : D[rs]) - CX[i];
+        }
+        if (r.emask & bit) {
+            // a row of several fluid runs: the site's own 18 offsets
+            const int e = r.fexc + __popcll(r.emask & below);
 #pragma unroll
-            for (int i = 1; i < Q; ++i) {
-                const int r = row_slot(i);
-                d[i - 1] = (r < 0 ? 0 : D[r]) - CX[i];
-            }
+            for (int i = 0; i < 18; ++i) d[i] = a.exc[(int64_t)i * a.n_exc_pad + e];
         }
     } else {
         using I = typename std::conditional<ADDR == ADDR_T16, int16_t, int32_t>::type;

@@ -6,6 +6,8 @@
 
 #include <cstdint>
 
+#include "d3q19.hpp"
+
 namespace lbm {
 
 // Per-instance wall parameters (Sec. 2.3, 2.4).
@@ -51,17 +53,15 @@ struct StepArgs {
     const double* kinv;     // 1 / k per stiffness index
     int64_t* clock;         // [2] steps executed before the current one
     // compressed addressing (see Compressed in builder.hpp)
-    const int32_t* wf_cur;
-    const int32_t* wf_firr;
-    const uint64_t* wf_smask;
-    const uint64_t* wf_imask;
+    const WfRec* wf;         // one record per 64 sites
     const int32_t* stretch;  // 8 per stretch
-    const int32_t* irr;      // 18 planes x n_irr_pad
-    int64_t n_irr_pad;
+    const uint32_t* nfm;     // per irregular site: non-fluid link mask
+    const int32_t* exc;      // 18 planes x n_exc_pad: offsets of exceptional sites
+    int64_t n_exc_pad;
 };
 
 // Addressing of the update kernel: per-site offset table of 16 or 32 bits,
-// or compressed (stretches + irregular-site table).
+// or compressed (stretches, link masks, exceptional-site table).
 enum { ADDR_T16 = 16, ADDR_T32 = 32, ADDR_COMP = 0 };
 
 struct FieldArgs {

@@ -83,13 +83,12 @@ struct lbm_ctx {
     float* bw = nullptr;
     int64_t nb = 0, n_irr = 0;
     // compressed addressing
-    int32_t* wf_cur = nullptr;
-    int32_t* wf_firr = nullptr;
-    uint64_t* wf_smask = nullptr;
-    uint64_t* wf_imask = nullptr;
+    WfRec* wf = nullptr;
     int32_t* stretch = nullptr;
-    int32_t* irr = nullptr;
-    int64_t n_irr_pad = 0, n_stretch = 0;
+    uint32_t* nfm = nullptr;
+    int32_t* exc = nullptr;
+    int64_t n_exc = 0, n_exc_pad = 0, n_stretch = 0;
+    Compressed comp;        // host copy of the compressed addressing
     int32_t* wsite = nullptr;
     double* wnormal = nullptr;
     int32_t* wk = nullptr;
@@ -192,12 +191,6 @@ int upload(lbm_ctx* c, void* dst, const void* src, size_t bytes) {
 int sync_tables(lbm_ctx* c) {
     if (!c->tables_dirty) return LBM_OK;
     const std::vector<int> m = modes(c);
-    {
-        std::vector<int32_t> t32;
-        build_device_nbr<int32_t>(c->plan, m, c->np, t32);
-        int rc = upload(c, c->nbr32, t32.data(), t32.size() * 4);
-        if (rc) return rc;
-    }
     if (c->have16) {
         std::vector<int16_t> t16;
         build_device_nbr<int16_t>(c->plan, m, c->np, t16);
@@ -208,11 +201,15 @@ int sync_tables(lbm_ctx* c) {
     build_device_nbr<int32_t>(c->plan, m, c->np, t32);
     BoundaryList bl;
     build_boundary(c->plan, m, c->seg_off, c->iolet_off, bl);
-    Compressed cm;
-    std::string e = build_compressed(c->plan, bl, t32, c->np, cm);
-    if (!e.empty()) return fail(c, LBM_EINVAL, "%s", e.c_str());
-    if ((int64_t)bl.site.size() != c->n_irr || cm.n_stretch != c->n_stretch)
-        return fail(c, LBM_ESTATE, "irregular-site set changed");
+    if ((int64_t)bl.site.size() != c->n_irr) return fail(c, LBM_ESTATE, "irregular-site set changed");
+    // the compressed form was built and checked against the full table when
+    // the buffers were sized; only its mode-dependent parts change here
+    Compressed& cm = c->comp;
+    refresh_compressed(bl, t32, c->np, cm);
+    {
+        int rc = upload(c, c->nbr32, t32.data(), t32.size() * 4);
+        if (rc) return rc;
+    }
     const int64_t ni = c->n_irr;
     c->nb = (int64_t)bl.ghost.size();
     int rc = upload(c, c->bj, bl.ghost.data(), c->nb * 4);
@@ -223,12 +220,10 @@ int sync_tables(lbm_ctx* c) {
     rc = rc ? rc : upload(c, c->bk, bl.kidx.data(), ni * 4);
     rc = rc ? rc : upload(c, c->bw, bl.weight.data(), ni * 4);
     const int64_t nwf = c->np / 64;
-    rc = rc ? rc : upload(c, c->wf_cur, cm.wf_cur.data(), nwf * 4);
-    rc = rc ? rc : upload(c, c->wf_firr, cm.wf_firr.data(), nwf * 4);
-    rc = rc ? rc : upload(c, c->wf_smask, cm.wf_smask.data(), nwf * 8);
-    rc = rc ? rc : upload(c, c->wf_imask, cm.wf_imask.data(), nwf * 8);
+    rc = rc ? rc : upload(c, c->wf, cm.wf.data(), nwf * sizeof(WfRec));
     rc = rc ? rc : upload(c, c->stretch, cm.stretch.data(), cm.stretch.size() * 4);
-    rc = rc ? rc : upload(c, c->irr, cm.irr.data(), cm.irr.size() * 4);
+    rc = rc ? rc : upload(c, c->nfm, cm.nfm.data(), cm.nfm.size() * 4);
+    rc = rc ? rc : upload(c, c->exc, cm.exc.data(), cm.exc.size() * 4);
     if (rc) return rc;
     c->tables_dirty = false;
     drop_graphs(c);
@@ -301,13 +296,11 @@ StepArgs step_args(const lbm_ctx* c, int parity) {
     a.iop = c->iop;
     a.kinv = c->kinv;
     a.clock = c->clock;
-    a.wf_cur = c->wf_cur;
-    a.wf_firr = c->wf_firr;
-    a.wf_smask = c->wf_smask;
-    a.wf_imask = c->wf_imask;
+    a.wf = c->wf;
     a.stretch = c->stretch;
-    a.irr = c->irr;
-    a.n_irr_pad = c->n_irr_pad;
+    a.nfm = c->nfm;
+    a.exc = c->exc;
+    a.n_exc_pad = c->n_exc_pad;
     return a;
 }
 
@@ -481,6 +474,48 @@ int lbm_plan_export(const lbm_instance_desc* inst, int n_inst, const int* wall_m
     return LBM_OK;
 }
 
+int lbm_plan_compressed(const lbm_instance_desc* inst, int n_inst, const int* wall_mode,
+                        int64_t* stats) {
+    if (!stats) return fail(nullptr, LBM_EINVAL, "stats is NULL");
+    Plan p;
+    std::string e = build_plan(inst, n_inst, p);
+    if (!e.empty()) return fail(nullptr, LBM_EINVAL, "%s", e.c_str());
+    std::vector<int> m(n_inst, LBM_WALL_BOUNCEBACK), so(n_inst, 0), io(n_inst, 0);
+    if (wall_mode)
+        for (int k = 0; k < n_inst; ++k) m[k] = wall_mode[k];
+    const int64_t np = std::max<int64_t>(256, (p.N + 255) / 256 * 256);
+    std::vector<int32_t> t32;
+    build_device_nbr<int32_t>(p, m, np, t32);
+    BoundaryList bl;
+    build_boundary(p, m, so, io, bl);
+    Compressed cm;
+    e = build_compressed(p, bl, t32, np, cm);
+    if (!e.empty()) return fail(nullptr, LBM_EINVAL, "%s", e.c_str());
+    // the runtime builds the form once for all-bounce-back walls and then
+    // refreshes it for the actual modes: both routes must agree
+    {
+        const std::vector<int> m0(n_inst, LBM_WALL_BOUNCEBACK);
+        std::vector<int32_t> t0;
+        build_device_nbr<int32_t>(p, m0, np, t0);
+        BoundaryList b0;
+        build_boundary(p, m0, so, io, b0);
+        Compressed c0;
+        e = build_compressed(p, b0, t0, np, c0);
+        if (!e.empty()) return fail(nullptr, LBM_EINVAL, "%s", e.c_str());
+        refresh_compressed(bl, t32, np, c0);
+        if (c0.nfm != cm.nfm || c0.exc != cm.exc || c0.stretch != cm.stretch ||
+            c0.wf.size() != cm.wf.size() ||
+            std::memcmp(c0.wf.data(), cm.wf.data(), cm.wf.size() * sizeof(WfRec)) != 0)
+            return fail(nullptr, LBM_EINVAL, "compressed addressing: refresh for the wall modes "
+                                             "differs from a direct build");
+    }
+    stats[0] = cm.n_stretch;
+    stats[1] = cm.n_irr;
+    stats[2] = cm.n_exc;
+    stats[3] = (int64_t)cm.wf.size();
+    return LBM_OK;
+}
+
 int lbm_create_geometry(lbm_ctx** out, const lbm_instance_desc* inst, int n_inst, int dtype,
                         double tau) {
     if (!out) return fail(nullptr, LBM_EINVAL, "out is NULL");
@@ -540,11 +575,12 @@ int lbm_create_geometry(lbm_ctx** out, const lbm_instance_desc* inst, int n_inst
         build_device_nbr<int32_t>(c->plan, m0, c->np, t32);
         BoundaryList bl;
         build_boundary(c->plan, m0, c->seg_off, c->iolet_off, bl);
-        Compressed cm;
+        Compressed& cm = c->comp;
         std::string ce = build_compressed(c->plan, bl, t32, c->np, cm);
         if (!ce.empty()) rc = fail(c, LBM_EINVAL, "%s", ce.c_str());
         c->n_irr = (int64_t)bl.site.size();
-        c->n_irr_pad = cm.n_irr_pad;
+        c->n_exc = cm.n_exc;
+        c->n_exc_pad = cm.n_exc_pad;
         c->n_stretch = cm.n_stretch;
         const int64_t ni = c->n_irr, nwf = c->np / 64;
         rc = rc ? rc : dalloc(c, (void**)&c->bj, ni * 4);
@@ -554,12 +590,10 @@ int lbm_create_geometry(lbm_ctx** out, const lbm_instance_desc* inst, int n_inst
         rc = rc ? rc : dalloc(c, (void**)&c->bio, ni * 4);
         rc = rc ? rc : dalloc(c, (void**)&c->bk, ni * 4);
         rc = rc ? rc : dalloc(c, (void**)&c->bw, ni * 4);
-        rc = rc ? rc : dalloc(c, (void**)&c->wf_cur, nwf * 4);
-        rc = rc ? rc : dalloc(c, (void**)&c->wf_firr, nwf * 4);
-        rc = rc ? rc : dalloc(c, (void**)&c->wf_smask, nwf * 8);
-        rc = rc ? rc : dalloc(c, (void**)&c->wf_imask, nwf * 8);
+        rc = rc ? rc : dalloc(c, (void**)&c->wf, nwf * sizeof(WfRec));
         rc = rc ? rc : dalloc(c, (void**)&c->stretch, cm.stretch.size() * 4);
-        rc = rc ? rc : dalloc(c, (void**)&c->irr, cm.irr.size() * 4);
+        rc = rc ? rc : dalloc(c, (void**)&c->nfm, cm.nfm.size() * 4);
+        rc = rc ? rc : dalloc(c, (void**)&c->exc, cm.exc.size() * 4);
     }
     if (c->have16) rc = rc ? rc : dalloc(c, &c->nbr16, (size_t)18 * c->np * 2);
     const int64_t nw = (int64_t)c->plan.wall_site.size();
@@ -878,9 +912,10 @@ int lbm_get_info(const lbm_ctx* c, lbm_info* info) {
     info->bytes_per_site_algorithmic = 2.0 * Q * (double)c->esize;
     const double N = (double)std::max<int64_t>(1, c->plan.N);
     if (c->ibits == 0)
-        info->bytes_per_site_model = 2.0 * Q * (double)c->esize + 24.0 / 64.0 +
+        info->bytes_per_site_model = 2.0 * Q * (double)c->esize + 48.0 / 64.0 +
                                      32.0 * (double)c->n_stretch / N +
-                                     (double)c->n_irr / N * (72.0 + 20.0);
+                                     (double)c->n_irr / N * (4.0 + 20.0) +
+                                     (double)c->n_exc / N * 72.0;
     else
         info->bytes_per_site_model = 2.0 * Q * (double)c->esize + 18.0 * (c->ibits / 8) +
                                      (double)c->nb / N * 24.0;

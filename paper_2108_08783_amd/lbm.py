@@ -31,6 +31,7 @@ EXPORTS = [
     "lbm_get_stream", "lbm_time_steps", "lbm_read_fields", "lbm_read_populations",
     "lbm_write_populations", "lbm_cycle_delta", "lbm_get_info", "lbm_instance_sites",
     "lbm_set_launch", "lbm_autotune", "lbm_plan_export", "lbm_copy_probe",
+    "lbm_plan_compressed",
 ]
 
 
@@ -106,6 +107,7 @@ def load():
         "lbm_set_launch": [P, I, I, I, I, I, I, I],
         "lbm_autotune": [P, I, P],
         "lbm_plan_export": [P, I, P, P, P, P, P],
+        "lbm_plan_compressed": [P, I, P, P],
         "lbm_copy_probe": [P, P, ctypes.c_size_t, I, I, P, P],
     }
     for name, args in sig.items():
@@ -281,6 +283,19 @@ def lbm_plan_export(geoms, wall_modes=None, tables=True):
                None)
         out.update(nbr=nbr, boundary=bs[:counts[1]], bmask=bm[:counts[1]])
     return out
+
+
+def lbm_plan_compressed(geoms, wall_modes=None):
+    """Host-only build (and self-check) of the update kernel's compressed
+    addressing: dict with stretches, irregular, exceptional and records."""
+    lib = load()
+    arr, keep = _descs(geoms)
+    wm = None if wall_modes is None else np.ascontiguousarray(wall_modes, np.int32)
+    st = np.zeros(4, np.int64)
+    _check(lib.lbm_plan_compressed(arr, len(geoms), _p(wm), _p(st)), None)
+    del keep
+    return dict(stretches=int(st[0]), irregular=int(st[1]), exceptional=int(st[2]),
+                records=int(st[3]))
 
 
 # ------------------------------------------------------------------ wrapper --

@@ -81,12 +81,15 @@ def sweep(seed=4, n=64, target_sites=20e6, period=PERIOD):
 
 
 def apply(lat: lbm.Lattice, wl: Workload, init=True):
+    # every wall mode first: a mode change rebuilds the tables of all
+    # instances at the next initialisation or step, so initialise after
     for k, p in enumerate(wl.params):
         lat.set_wall(k, p.mode, F=p.F, P0=p.P0, k=p.k)
         for i, q in p.iolets.items():
             lat.set_iolet(k, i, q["kind"], q["a0"], q.get("amp", 0.0), q.get("period", 1.0),
                           q.get("phase", 0.0), q.get("direction"))
-        if init:
+    if init:
+        for k in range(len(wl.params)):
             lat.init_fields(k)
 
 

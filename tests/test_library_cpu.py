@@ -139,3 +139,31 @@ def test_invalid_arguments_are_rejected_without_a_device(bad):
 def test_plan_rejects_zero_instances():
     with pytest.raises(lbm.LbmError):
         lbm.lbm_plan_export([], tables=False)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_compressed_addressing_reproduces_the_table(mode):
+    """The compressed addressing (stretches, non-fluid link masks, full
+    offsets for rows of several fluid runs) is checked against the full
+    neighbour table at every site by the builder itself; random boxes have
+    many multi-run rows, convex tubes none."""
+    rng = np.random.default_rng(7 + mode)
+    for _ in range(4):
+        g = inputs.separate_iolets(inputs.random_labels((12, 9, 10), rng, p_fluid=0.7))
+        st = lbm.lbm_plan_compressed([g], [mode])
+        n = lbm.lbm_plan_export([g], wall_modes=[mode], tables=False)["n_sites"]
+        assert st["records"] == (max(256, (n + 255) // 256 * 256)) // 64
+        assert 0 < st["exceptional"] <= st["irregular"] <= n
+    tube = inputs.cylinder(8, 64)
+    st = lbm.lbm_plan_compressed([tube], [mode])
+    assert st["exceptional"] == 0               # every row of a convex section is one run
+    assert st["irregular"] == 3858
+    assert st["stretches"] <= 2 * 17 * 64      # about one per row
+
+
+def test_compressed_addressing_of_a_batch():
+    geos, _ = inputs.batch(5, n=6, target_sites=2e5)
+    st = lbm.lbm_plan_compressed(geos, [1] * len(geos))
+    n = lbm.lbm_plan_export(geos, wall_modes=[1] * len(geos), tables=False)["n_sites"]
+    assert st["records"] * 64 >= n
+    assert st["exceptional"] < 0.01 * st["irregular"]
