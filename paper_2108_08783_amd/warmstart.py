@@ -10,25 +10,27 @@ state, and the figure of merit is the number of cardiac cycles needed.
 Features (16 per site, host-side, from the generator's segment list):
   0  (r(t) - |x - q|) / r(t): wall distance relative to the local radius
   1  r(t) / 24: local radius
-  2  r(t) / r_inlet: radius relative to the inlet (under Murray's law the
-     mean velocity of a branch scales with it)
+  2  r(t) / r_inlet: radius relative to the inlet
   3  t: position along the owning segment (0 at its start)
   4  path position: distance from the inlet along the tree over the
      (mean) inlet-to-outlet path length through the segment
-  5  downstream Poiseuille pressure estimate over u0: the sum of
-     8 nu L / (r_inlet r) over the rest of the segment and the mean path to
-     the outlets (Murray flow split), scaled by 1/2
+  5  the prior's density output (below)
   6  downstream path length over r_inlet, scaled by 1/40
-  7-11 generation one-hot (0..4, deeper generations share slot 4)
+  7-9 generation one-hot (0, 1, deeper); the deeper slot starts at zero
+     weight, so generations absent from the training data contribute
+     nothing
+  10 the prior's axial velocity over u0
+  11 the prior's slip factor at the local mean pressure
   12 log10(k) + 2: wall stiffness of the segment
   13 u0 / 0.02: inlet amplitude
   14, 15 sin and cos of 2 pi (phase of the predicted state in the cycle)
 Outputs (4): (rho - 1) / (10 u0), and the velocity / u0 in the segment's
-frame (axial, radial, azimuthal), each as a correction to a physics prior:
-the quasi-steady Poiseuille state of the tree with Murray flow split,
-  u_axial = 2 u_mean (1 - (|x - q| / r)^2), u_mean = u_in(phase) r / r_inlet,
-  p - p_out = u_in(phase) * (downstream Poiseuille pressure estimate),
-so that sites unlike the training data fall back toward the prior.
+frame (axial, radial, azimuthal), each as a correction to a physics prior
+(`network_prior`): a linear one-dimensional model of the segment tree with
+slip-Poiseuille mean flow and, at the drive frequency, a transmission line
+per segment with the slip Womersley impedance and the lattice's
+compressibility.  Sites unlike the training data fall back toward the
+prior.
 """
 from __future__ import annotations
 
@@ -49,17 +51,16 @@ N_FEAT, N_OUT = 16, 4
 # ------------------------------------------------------------- features --
 @dataclasses.dataclass
 class SiteFrame:
-    static: np.ndarray   # [n, 12] features 0..11
+    static: np.ndarray   # [n, 12] float32, features 0..11
     seg: np.ndarray      # [n] owning segment
     axis: np.ndarray     # [n, 3]
     radial: np.ndarray   # [n, 3]
     azim: np.ndarray     # [n, 3]
 
 
-def _path_lengths(segs, nu):
-    """Per segment: distance from the inlet to its start, its length, the
-    mean inlet-to-outlet path length through it, and the downstream
-    Poiseuille pressure (per unit inlet velocity) and length from its end."""
+def _topology(segs):
+    """Parent of every segment (-1 for the root) and the children lists;
+    a segment's parent is the one whose end point is its start point."""
     n = len(segs)
     parent = [-1] * n
     for j, s in enumerate(segs):
@@ -67,67 +68,104 @@ def _path_lengths(segs, nu):
             if i != j and np.allclose(q.p1, s.p0):
                 parent[j] = i
                 break
+    children = [[j for j in range(n) if parent[j] == i] for i in range(n)]
+    return parent, children
+
+
+def _path_lengths(segs):
+    """Per segment: distance from the inlet to its start, its length, the
+    mean inlet-to-outlet path length through it and the mean remaining
+    length beyond its end."""
+    n = len(segs)
+    parent, children = _topology(segs)
     lengths = [float(np.linalg.norm(s.p1 - s.p0)) for s in segs]
-    r_in = segs[0].r0
-    res = [8.0 * nu * lengths[i] / (r_in * 0.5 * (segs[i].r0 + segs[i].r1)) for i in range(n)]
     start = [0.0] * n
     for j in range(n):            # parents precede children in the lists
         if parent[j] >= 0:
             start[j] = start[parent[j]] + lengths[parent[j]]
-    children = [[j for j in range(n) if parent[j] == i] for i in range(n)]
     rem = [0.0] * n
-    pend = [0.0] * n
     for i in range(n - 1, -1, -1):
         if children[i]:
             rem[i] = float(np.mean([lengths[c] + rem[c] for c in children[i]]))
-            pend[i] = float(np.mean([res[c] + pend[c] for c in children[i]]))
     total = [start[i] + lengths[i] + rem[i] for i in range(n)]
-    return start, lengths, total, res, pend, rem
+    return start, lengths, total, rem
 
 
-def site_frames(geo: inputs.Geometry, nu: float = 0.1) -> SiteFrame:
+def site_frames(geo: inputs.Geometry) -> SiteFrame:
     segs = geo.segments
     assert segs, "geometry needs its segment list"
     zz, yy, xx = np.nonzero(geo.labels == inputs.FLUID)
     pos = np.stack([xx, yy, zz], 1).astype(np.float64)
+    n_id = max(s.sid for s in segs) + 1
+    # per-segment constants, gathered per site (segments are few)
+    P0 = np.zeros((n_id, 3))
+    A = np.zeros((n_id, 3))
+    Ls = np.ones(n_id)
+    R0 = np.zeros(n_id)
+    R1 = np.zeros(n_id)
+    G = np.zeros(n_id, np.int64)
+    FB = np.zeros((n_id, 3))
+    for sg in segs:
+        d = np.asarray(sg.p1, np.float64) - np.asarray(sg.p0, np.float64)
+        L = float(np.linalg.norm(d))
+        ax = d / L
+        fb = np.cross(ax, [0, 0, 1.0] if abs(ax[2]) < 0.9 else [0, 1.0, 0])
+        P0[sg.sid], A[sg.sid], Ls[sg.sid] = sg.p0, ax, L
+        R0[sg.sid], R1[sg.sid], G[sg.sid] = sg.r0, sg.r1, sg.gen
+        FB[sg.sid] = fb / np.linalg.norm(fb)
     sid = geo.segment[zz, yy, xx].astype(np.int64)
+    del xx, yy, zz
     n = len(sid)
-    p0 = np.array([s.p0 for s in segs])[sid]
-    p1 = np.array([s.p1 for s in segs])[sid]
-    r0 = np.array([s.r0 for s in segs])[sid]
-    r1 = np.array([s.r1 for s in segs])[sid]
-    gen = np.array([s.gen for s in segs])[sid]
-    d = p1 - p0
-    L = np.linalg.norm(d, axis=1)
-    a = d / L[:, None]
-    t = np.clip(((pos - p0) * a).sum(1) / L, 0.0, 1.0)
-    q = p0 + t[:, None] * d
-    rv = pos - q
-    dist = np.linalg.norm(rv, axis=1)
-    r = r0 + t * (r1 - r0)
-    fallback = np.cross(a, np.where(np.abs(a[:, 2:3]) < 0.9, [[0, 0, 1.0]], [[0, 1.0, 0]]))
-    fallback /= np.linalg.norm(fallback, axis=1, keepdims=True)
-    radial = np.where(dist[:, None] > 1e-9, rv / np.maximum(dist, 1e-12)[:, None], fallback)
-    azim = np.cross(a, radial)
-    start, lengths, total, res, pend, rem = (np.array(v)[sid] for v in _path_lengths(segs, nu))
+    a = A[sid]
+    rv = pos - P0[sid]
+    del pos
+    s_ax = np.einsum("ij,ij->i", rv, a)
+    t = np.clip(s_ax / Ls[sid], 0.0, 1.0)
+    rv -= (t * Ls[sid])[:, None] * a
+    dist = np.sqrt(np.einsum("ij,ij->i", rv, rv))
+    r = R0[sid] + t * (R1[sid] - R0[sid])
+    gen = G[sid]
+    ok = dist > 1e-9
+    radial = rv
+    np.divide(rv, dist[:, None], out=radial, where=ok[:, None])
+    bad = np.nonzero(~ok)[0]
+    radial[bad] = FB[sid[bad]]
+    azim = np.empty_like(a)
+    azim[:, 0] = a[:, 1] * radial[:, 2] - a[:, 2] * radial[:, 1]
+    azim[:, 1] = a[:, 2] * radial[:, 0] - a[:, 0] * radial[:, 2]
+    azim[:, 2] = a[:, 0] * radial[:, 1] - a[:, 1] * radial[:, 0]
+    ids = [sg.sid for sg in segs]
+    by_id = []
+    for v in _path_lengths(segs):
+        w = np.zeros(n_id)
+        w[ids] = v
+        by_id.append(w[sid])
+    start, lengths, total, rem = by_id
     path = (start + t * lengths) / total
     r_in = segs[0].r0
-    static = np.zeros((n, 12))
+    static = np.zeros((n, 12), np.float32)
     static[:, 0] = np.clip((r - dist) / r, -0.5, 1.0)
     static[:, 1] = r / 24.0
     static[:, 2] = r / r_in
     static[:, 3] = t
     static[:, 4] = path
-    static[:, 5] = 0.5 * (res * (1.0 - t) + pend)
     static[:, 6] = (lengths * (1.0 - t) + rem) / r_in / 40.0
-    static[np.arange(n), 7 + np.minimum(gen, 4)] = 1.0
+    static[:, 7] = gen == 0
+    static[:, 8] = gen == 1
+    static[:, 9] = gen >= 2
     return SiteFrame(static, sid, a, radial, azim)
 
 
-def features(frame: SiteFrame, k_seg: Sequence[float], u0: float, phase: float) -> np.ndarray:
+def features(frame: SiteFrame, k_seg: Sequence[float], u0: float, phase: float,
+             prior: "Prior") -> np.ndarray:
+    """Network inputs (listed in the module docstring); `prior` is
+    `network_prior`'s estimate for the same sites and phase."""
     n = frame.static.shape[0]
     X = np.empty((n, N_FEAT), np.float32)
     X[:, :12] = frame.static
+    X[:, 5] = prior.Y[:, 0]
+    X[:, 10] = prior.Y[:, 1]
+    X[:, 11] = prior.slip
     X[:, 12] = np.log10(np.asarray(k_seg, np.float64)[frame.seg]) + 2.0
     X[:, 13] = u0 / 0.02
     X[:, 14] = math.sin(2 * math.pi * phase)
@@ -135,15 +173,174 @@ def features(frame: SiteFrame, k_seg: Sequence[float], u0: float, phase: float) 
     return X
 
 
-def prior(frame: SiteFrame, phase: float, amp: float = 0.5) -> np.ndarray:
-    """Quasi-steady Poiseuille/Murray estimate in output units."""
+def _b2(R, s):
+    """b^2 of the parabola A (b^2 - y^2) whose value at the wall node R_w =
+    R + 1/2 is s times its value at R_w - 1 (the slip condition of the wall
+    rule, Sec. 2.3); large for s -> 1 (plug flow)."""
+    Rw = R + 0.5
+    return (Rw * Rw - s * (Rw - 1.0) ** 2) / np.maximum(1.0 - s, 1e-9)
+
+
+def _slip(p, k, F, P0):
+    """Slip factor of the elastic rule at pressure p (Sec. 2.3 and 2.4):
+    s = (F + Delta E)/(1 + Delta E), Delta E = max(0, (p - P0)/k)."""
+    dE = np.maximum(0.0, (p - P0) / k)
+    return (F + dE) / (1.0 + dE)
+
+
+def _womersley(r, s, kw):
+    """Oscillatory profile u(y) = C0 (1 + beta J0(kw y)) of a tube of radius
+    r whose wall node R_w = r + 1/2 carries s times the velocity of the node
+    inside it; kw^2 = -i omega / nu.  Returns (beta, m) with m the mean of
+    the profile over the disk y < r divided by C0."""
+    from scipy.special import jv
+    Rw = r + 0.5
+    beta = -(1.0 - s) / (jv(0, kw * Rw) - s * jv(0, kw * (Rw - 1.0)))
+    m = 1.0 + beta * 2.0 * jv(1, kw * r) / (kw * r)
+    return beta, m
+
+
+@dataclasses.dataclass
+class Prior:
+    Y: np.ndarray        # [n, 4] estimate in output units
+    slip: np.ndarray     # [n] slip factor at the mean pressure
+
+
+def network_prior(geo: inputs.Geometry, frame: SiteFrame, k_seg, F: float, P0: float, u0: float,
+                  phase: float, nu: float = 0.1, amp: float = 0.5, period: float = 4000.0,
+                  n_sub: int = 16, iters: int = 4) -> Prior:
+    """Linear one-dimensional model of the segment tree, evaluated at every
+    site.  Inlet flow Q(t) = pi r_in^2 u0 (1 + amp sin(omega t)); pressure
+    P0 at the outlets.
+
+    Mean part: slip Poiseuille flow in each piece (n_sub pieces per
+    segment), -dp/dx = 4 nu Q / (pi r^2 (b^2 - r^2/2)) with b^2 from the
+    slip factor at the local mean pressure; flows split at junctions by the
+    downstream resistances, iterated with the pressures.
+    Oscillating part: a transmission line per piece at the drive frequency,
+    series impedance i omega / (pi r^2 m) from the slip Womersley profile
+    and shunt admittance i omega pi r^2 / c_s^2 from the lattice's
+    compressibility (c_s^2 = 1/3); input impedances from the outlets up,
+    then pressure and flow from the inlet down."""
+    segs = geo.segments
+    n = len(segs)
+    parent, children = _topology(segs)
+    omega = 2.0 * math.pi / period
+    kw = np.sqrt(-1j * omega / nu)
+    r_in = segs[0].r0
+    L = np.array([float(np.linalg.norm(sg.p1 - sg.p0)) for sg in segs])
+    k = np.asarray(k_seg, np.float64)[[sg.sid for sg in segs]]
+    tm = (np.arange(n_sub) + 0.5) / n_sub                      # piece mid-points
+    rp = np.array([sg.r0 + tm * (sg.r1 - sg.r0) for sg in segs])          # [n, n_sub]
+    lp = (L / n_sub)[:, None]
+    A = math.pi * rp * rp
+    Q0 = math.pi * r_in * r_in * u0
+
+    # ---- mean flow: pressures from the outlets up, flow split by resistance
+    Q = np.zeros(n)
+    Q[0] = Q0
+    for i in range(n):                       # Murray split to start
+        if children[i]:
+            w = np.array([segs[c].r0 ** 3 for c in children[i]])
+            Q[children[i]] = Q[i] * w / w.sum()
+    pst = np.zeros((n, n_sub + 1))
+    slp = np.zeros((n, n_sub))
+    for _ in range(iters):
+        for i in range(n - 1, -1, -1):
+            p = P0 if not children[i] else float(np.mean([pst[c, 0] for c in children[i]]))
+            pst[i, n_sub] = p
+            for m in range(n_sub - 1, -1, -1):
+                sl = float(_slip(p, k[i], F, P0))
+                b2 = float(_b2(rp[i, m], sl))
+                G = 4.0 * nu * Q[i] / (A[i, m] * max(b2 - 0.5 * rp[i, m] ** 2, 1e-9))
+                p += G * lp[i, 0]
+                pst[i, m] = p
+                slp[i, m] = sl
+        Rseg = (pst[:, 0] - pst[:, n_sub]) / np.maximum(Q, 1e-30)
+        Req = np.zeros(n)
+        for i in range(n - 1, -1, -1):
+            down = 1.0 / sum(1.0 / Req[c] for c in children[i]) if children[i] else 0.0
+            Req[i] = Rseg[i] + down
+        for i in range(n):
+            if children[i]:
+                g = np.array([1.0 / Req[c] for c in children[i]])
+                Q[children[i]] = Q[i] * g / g.sum()
+
+    # ---- oscillating flow at the drive frequency
+    beta, mfac = _womersley(rp, slp, kw)
+    Z = 1j * omega / (A * mfac)              # series impedance per length
+    Y = 1j * omega * A * 3.0                 # shunt admittance per length
+    gam = np.sqrt(Z * Y)
+    Zc = np.sqrt(Z / Y)
+    th = np.tanh(gam * lp)
+    Zst = np.zeros((n, n_sub + 1), complex)  # impedance looking downstream
+    for i in range(n - 1, -1, -1):
+        if children[i]:
+            ZL = 1.0 / sum(1.0 / Zst[c, 0] for c in children[i])
+        elif segs[i].outlet:
+            ZL = 0.0
+        else:
+            ZL = np.inf
+        Zst[i, n_sub] = ZL
+        for m in range(n_sub - 1, -1, -1):
+            if np.isinf(ZL):
+                ZL = Zc[i, m] / th[i, m]
+            else:
+                ZL = Zc[i, m] * (ZL + Zc[i, m] * th[i, m]) / (Zc[i, m] + ZL * th[i, m])
+            Zst[i, m] = ZL
+    ph = np.zeros((n, n_sub + 1), complex)
+    qh = np.zeros((n, n_sub + 1), complex)
+    for i in range(n):
+        if parent[i] < 0:
+            qh[i, 0] = -1j * amp * Q0            # amp sin = Re(-i amp e^{i omega t})
+            ph[i, 0] = Zst[i, 0] * qh[i, 0]
+        else:
+            ph[i, 0] = ph[parent[i], n_sub]
+            qh[i, 0] = ph[i, 0] / Zst[i, 0]
+        for m in range(n_sub):
+            ch, sh = np.cosh(gam[i, m] * lp[i, 0]), np.sinh(gam[i, m] * lp[i, 0])
+            ph[i, m + 1] = ph[i, m] * ch - Zc[i, m] * qh[i, m] * sh
+            qh[i, m + 1] = qh[i, m] * ch - ph[i, m] / Zc[i, m] * sh
+
+    # ---- evaluate at the sites
     st = frame.static
-    drive = 1.0 + amp * math.sin(2 * math.pi * phase)
-    s = np.clip(1.0 - st[:, 0], 0.0, 1.0)            # |x - q| / r
-    P = np.zeros((st.shape[0], N_OUT), np.float32)
-    P[:, 0] = 3.0 * (2.0 * st[:, 5]) * drive / 10.0   # 3 dp / (10 u0), dp/u0 = 2 f5
-    P[:, 1] = 2.0 * drive * st[:, 2] * (1.0 - s * s)
-    return P
+    seg = frame.seg
+    idx = np.array([sg.sid for sg in segs])
+    row = np.empty(int(idx.max()) + 1, np.int64)
+    row[idx] = np.arange(n)
+    g = row[seg]
+    r = 24.0 * st[:, 1].astype(np.float64)
+    t = st[:, 3].astype(np.float64)
+    dist = np.maximum(r * (1.0 - st[:, 0]), 0.0)
+    pos = t * n_sub
+    s0 = np.clip(np.floor(pos).astype(np.int64), 0, n_sub - 1)
+    fr = pos - s0
+    p_mean = pst[g, s0] * (1 - fr) + pst[g, s0 + 1] * fr
+    p_osc = ph[g, s0] * (1 - fr) + ph[g, s0 + 1] * fr
+    q_osc = qh[g, s0] * (1 - fr) + qh[g, s0 + 1] * fr
+    sl = _slip(p_mean, k[g], F, P0)
+    b2 = _b2(r, sl)
+    area = math.pi * r * r
+    prof = np.clip((b2 - dist * dist) / np.maximum(b2 - 0.5 * r * r, 1e-9), 0.0, None)
+    # beta and m at the piece mid-points, J0(kw y) from a fine table
+    sm = np.clip(np.floor(pos - 0.5).astype(np.int64), 0, n_sub - 2) if n_sub > 1 else 0 * s0
+    fm = np.clip(pos - 0.5 - sm, 0.0, 1.0) if n_sub > 1 else 0.0 * fr
+    bet = beta[g, sm] * (1 - fm) + beta[g, np.minimum(sm + 1, n_sub - 1)] * fm
+    mf = mfac[g, sm] * (1 - fm) + mfac[g, np.minimum(sm + 1, n_sub - 1)] * fm
+    from scipy.special import jv
+    h = 1.0 / 64.0
+    ytab = np.arange(0.0, float(dist.max()) + 2 * h, h)
+    j0 = jv(0, kw * ytab)
+    yi = np.minimum((dist / h).astype(np.int64), len(ytab) - 2)
+    yf = dist / h - yi
+    shape = (1.0 + bet * (j0[yi] * (1 - yf) + j0[yi + 1] * yf)) / mf
+    e = np.exp(1j * 2.0 * math.pi * phase)
+    u_ax = Q[g] / area * prof + np.real(q_osc / area * shape * e)
+    p = p_mean + np.real(p_osc * e)
+    P = np.zeros((len(seg), N_OUT), np.float32)
+    P[:, 0] = (3.0 * p - 1.0) / (10.0 * u0)
+    P[:, 1] = u_ax / u0
+    return Prior(P, sl.astype(np.float32))
 
 
 def targets(frame: SiteFrame, rho, u, u0) -> np.ndarray:
@@ -216,6 +413,7 @@ def collect_batch(wl: workloads.Workload, dtype="f16", phases=8, sites_per_phase
     PeriodicResult).  All instances share the drive period."""
     rng = np.random.default_rng(seed)
     period = int(wl.params[0].iolets[0]["period"])
+    nu = (wl.tau - 0.5) / 3.0
     lat = workloads.lattice(wl, dtype)
     lat.autotune(64)
     res = run_to_periodic(lat, len(wl.geoms), period, tol, max_cycles, log=log)
@@ -238,14 +436,16 @@ def collect_batch(wl: workloads.Workload, dtype="f16", phases=8, sites_per_phase
             rho, u, _, _ = lat.read_fields(k, wss=False, wall_dr=False)
             idx, sub = subs[k]
             u0 = p.iolets[0]["a0"]
-            Xs.append(features(sub, p.k, u0, phase))
-            Ts.append(targets(sub, rho[idx], u[idx], u0) - prior(sub, phase))
+            pr = network_prior(wl.geoms[k], sub, p.k, p.F, p.P0, u0, phase, nu=nu,
+                               amp=p.iolets[0]["amp"], period=period)
+            Xs.append(features(sub, p.k, u0, phase, pr))
+            Ts.append(targets(sub, rho[idx], u[idx], u0) - pr.Y)
         lat.step(step)
     lat.close()
     return np.concatenate(Xs), np.concatenate(Ts), res
 
 
-GEN_SLOTS = range(7, 12)
+GEN_SLOTS = range(7, 10)
 TRUST = 1.0
 
 
@@ -288,52 +488,70 @@ def train(net, X: np.ndarray, T: np.ndarray, epochs=30, batch=8192, lr=2e-3, see
     return losses
 
 
-def predict(net, frame: SiteFrame, k_seg, u0, phase, chunk=1 << 20):
-    """Network prediction (rho, u) of every site of one instance."""
+def instance_prior(geo, frame: SiteFrame, params, phase, nu=0.1) -> Prior:
+    io = params.iolets[0]
+    return network_prior(geo, frame, params.k, params.F, params.P0, io["a0"], phase, nu=nu,
+                         amp=io["amp"], period=io["period"])
+
+
+def predict(net, geo, frame: SiteFrame, params, phase, nu=0.1, chunk=1 << 20, use_net=True,
+            prior: Optional[Prior] = None):
+    """(rho, u) of every site of one instance: the network prior plus the
+    network's correction (clipped to the trust region)."""
     import torch
-    X = features(frame, k_seg, u0, phase)
-    Y = prior(frame, phase)
-    for s in range(0, X.shape[0], chunk):
-        xb = net.to_bf16(torch.tensor(X[s:s + chunk], device="cuda"))
-        # trust region: the correction to the prior is at most one output
-        # unit (u0 in velocity, 10 u0 in density)
-        Y[s:s + chunk] += np.clip(net.forward(xb).cpu().numpy(), -TRUST, TRUST)
+    u0 = params.iolets[0]["a0"]
+    pr = prior if prior is not None else instance_prior(geo, frame, params, phase, nu)
+    Y = pr.Y.copy()
+    if use_net:
+        X = features(frame, params.k, u0, phase, pr)
+        for s in range(0, X.shape[0], chunk):
+            xb = net.to_bf16(torch.tensor(X[s:s + chunk], device="cuda"))
+            # trust region: the correction to the prior is at most one output
+            # unit (u0 in velocity, 10 u0 in density)
+            Y[s:s + chunk] += np.clip(net.forward(xb).cpu().numpy(), -TRUST, TRUST)
     return assemble(frame, Y, u0)
 
 
 def compare_starts(net, wl: workloads.Workload, dtype="f32", tol=1e-3, max_cycles=20, log=None,
                    modes=("cold", "prior", "warm")):
     """Starts the same instances from rest ("cold"), from the physics prior
-    alone ("prior") and from the network ("warm"), runs each to periodicity
-    and returns the PeriodicResult per mode plus, per instance, the largest
-    difference of each periodic state from the cold one (max |du| / max |u|
-    at the same phase)."""
+    alone ("prior") and from the network ("warm") on one lattice
+    (re-initialised per start), runs each to periodicity and returns the
+    PeriodicResult per mode plus, per instance, the largest difference of
+    each periodic state from the cold one (max |du| / max |u| at the same
+    phase)."""
     period = int(wl.params[0].iolets[0]["period"])
+    nu = (wl.tau - 0.5) / 3.0
     out = {"state_diff": []}
     fields = {}
-    for mode in modes:
-        lat = workloads.lattice(wl, dtype)
-        lat.autotune(64)
-        if mode != "cold":
+    lat = workloads.lattice(wl, dtype)
+    lat.autotune(64)
+    frames, priors = {}, {}
+    if any(m != "cold" for m in modes):
+        for k, (g, p) in enumerate(zip(wl.geoms, wl.params)):
+            frames[k] = site_frames(g)
+            priors[k] = instance_prior(g, frames[k], p, 0.0, nu)
+    try:
+        for mode in modes:
             for k, (g, p) in enumerate(zip(wl.geoms, wl.params)):
-                fr = site_frames(g)
-                u0 = p.iolets[0]["a0"]
-                if mode == "warm":
-                    rho, u = predict(net, fr, p.k, u0, 0.0)
+                if mode == "cold":
+                    lat.init_fields(k)
                 else:
-                    rho, u = assemble(fr, prior(fr, 0.0), u0)
-                lat.init_fields(k, rho, u)
-        try:
-            res = run_to_periodic(lat, len(wl.geoms), period, tol, max_cycles, log=log)
-            # periodic states compared at the same phase (whole cycles from t=0)
-            fields[mode] = [lat.read_fields(k, wss=False, wall_dr=False)[1]
-                            for k in range(len(wl.geoms))]
-        except lbm.Diverged as e:
-            if log:
-                log(f"{mode} start diverged: {e}")
-            res = PeriodicResult([-2] * len(wl.geoms), [], 0.0)
-            fields[mode] = None
-        out[mode] = res
+                    rho, u = predict(net, g, frames[k], p, 0.0, nu=nu, use_net=(mode == "warm"),
+                                     prior=priors[k])
+                    lat.init_fields(k, rho, u)
+            try:
+                res = run_to_periodic(lat, len(wl.geoms), period, tol, max_cycles, log=log)
+                # periodic states compared at the same phase (whole cycles from t=0)
+                fields[mode] = [lat.read_fields(k, wss=False, wall_dr=False)[1]
+                                for k in range(len(wl.geoms))]
+            except lbm.Diverged as e:
+                if log:
+                    log(f"{mode} start diverged: {e}")
+                res = PeriodicResult([-2] * len(wl.geoms), [], 0.0)
+                fields[mode] = None
+            out[mode] = res
+    finally:
         lat.close()
     for k in range(len(wl.geoms)):
         uc = fields["cold"][k] if fields.get("cold") else None
@@ -344,82 +562,121 @@ def compare_starts(net, wl: workloads.Workload, dtype="f32", tol=1e-3, max_cycle
 
 
 # ------------------------------------------------------------- experiment --
+MODES = ("cold", "prior", "warm")
+
+
+def load_net(params):
+    """Network with the standard shape and the given parameters."""
+    from . import mlp
+    return mlp.Net(N_FEAT, 128, 4, N_OUT, params=np.asarray(params, np.float64))
+
+
+def _evaluate(net, wl, dtype, max_cycles, group, log):
+    cmp = compare_starts(net, wl, dtype, max_cycles=max_cycles, modes=MODES)
+    for m in MODES:
+        group[m] += cmp[m].cycles
+        group[m + "_du"] += cmp[m].du
+        group[m + "_dp"] += cmp[m].dp
+    group["state_diff"] += cmp["state_diff"]
+    group["sites"] += [g.n_fluid for g in wl.geoms]
+    return cmp
+
+
+def summarize(results):
+    """Aggregate figures of the per-instance results of one or more runs."""
+    out = {}
+    allc = {m: [] for m in MODES}
+    for name in ("sweep", "trees"):
+        r = results.get(name)
+        if not r or not r["cold"]:
+            continue
+        for m in MODES:
+            allc[m] += r[m]
+        ok = [i for i in range(len(r["cold"])) if all(r[m][i] > 0 for m in MODES)]
+        out[name] = dict(n=len(r["cold"]), **{
+            f"cycles_{m}_mean": float(np.mean([r[m][i] for i in ok])) if ok else None
+            for m in MODES})
+        out[name]["warm_fewer"] = sum(r["warm"][i] < r["cold"][i] for i in ok)
+        out[name]["warm_more"] = sum(r["warm"][i] > r["cold"][i] for i in ok)
+    ok = [i for i in range(len(allc["cold"])) if all(allc[m][i] > 0 for m in MODES)]
+    out["all_converged"] = len(ok) == len(allc["cold"])
+    for m in MODES:
+        out[f"cycles_{m}_mean"] = float(np.mean([allc[m][i] for i in ok])) if ok else None
+    out["median_ratio"] = (float(np.median([allc["warm"][i] / allc["cold"][i] for i in ok]))
+                           if ok else None)
+    diffs = [d for name in ("sweep", "trees") if results.get(name)
+             for d in results[name]["state_diff"]]
+    out["max_state_diff"] = float(max(diffs)) if diffs else None
+    return out
+
+
 def experiment(train_batches=4, train_per_batch=64, train_sites=20e6, test_sweep=16,
-               test_sweep_sites=5e6, test_trees=16, tree_scale=1.0, dtype="f32", epochs=30,
-               sites_per_phase=2048, max_cycles=12, seed=0, log=print):
+               test_sweep_sites=5e6, test_trees=16, tree_first=0, tree_scale=1.0, dtype="f32",
+               epochs=30, sites_per_phase=2048, max_cycles=12, seed=0, net_params=None,
+               save_net=None, log=print):
     """Train on cold-started sweep batches (seeds 1000.., run to
-    periodicity, sampled at 8 phases), then compare cold and warm starts on
-    held-out sweep instances (seed 3000) and Murray trees (seeds 2000..).
-    Returns a JSON-ready dict."""
+    periodicity, sampled at 8 phases) unless `net_params` is given, then
+    start held-out sweep instances (seed 3000) and Murray trees (seeds
+    2000 + tree_first ..) cold, from the prior and from the network, and
+    run each to periodicity.  The trained parameters are written to
+    `save_net` (.npy) before the evaluation starts.  Returns (JSON-ready
+    dict, network)."""
     t_all = time.perf_counter()
-    Xs, Ts, train_cycles = [], [], []
-    t0 = time.perf_counter()
-    for b in range(train_batches):
-        wl = workloads.sweep(seed=1000 + b, n=train_per_batch, target_sites=train_sites)
-        X, T, res = collect_batch(wl, dtype, sites_per_phase=sites_per_phase,
-                                  max_cycles=max_cycles, seed=b)
-        Xs.append(X)
-        Ts.append(T)
-        train_cycles += res.cycles
-        log(f"[warmstart] train batch {b}: {wl.n_sites} sites, cold cycles "
-            f"median {np.median(res.cycles):.0f}, {res.seconds:.1f}s")
-    X, T = np.concatenate(Xs), np.concatenate(Ts)
-    t_data = time.perf_counter() - t0
-    net = new_net(seed=seed)
-    t0 = time.perf_counter()
-    losses = train(net, X, T, epochs=epochs, log=lambda m: log("[warmstart] " + m)
-                   if m.startswith("epoch") and (int(m.split()[1][:-1]) % 5 == 0) else None)
-    t_train = time.perf_counter() - t0
-    # held-out evaluation
+    out = dict(config=dict(train_instances=train_batches * train_per_batch,
+                           train_sites_per_batch=train_sites, test_sweep=test_sweep,
+                           test_sweep_sites=test_sweep_sites, test_trees=test_trees,
+                           tree_first=tree_first, tree_scale=tree_scale, dtype=dtype,
+                           epochs=epochs, sites_per_phase=sites_per_phase, tol=1e-3,
+                           period=int(workloads.PERIOD)))
+    if net_params is None:
+        Xs, Ts, train_cycles = [], [], []
+        t0 = time.perf_counter()
+        for b in range(train_batches):
+            wl = workloads.sweep(seed=1000 + b, n=train_per_batch, target_sites=train_sites)
+            X, T, res = collect_batch(wl, dtype, sites_per_phase=sites_per_phase,
+                                      max_cycles=max_cycles, seed=b)
+            Xs.append(X)
+            Ts.append(T)
+            train_cycles += res.cycles
+            log(f"[warmstart] train batch {b}: {wl.n_sites} sites, cold cycles "
+                f"median {np.median(res.cycles):.0f}, {res.seconds:.1f}s")
+        X, T = np.concatenate(Xs), np.concatenate(Ts)
+        t_data = time.perf_counter() - t0
+        net = new_net(seed=seed)
+        t0 = time.perf_counter()
+        losses = train(net, X, T, epochs=epochs, log=lambda m: log("[warmstart] " + m)
+                       if m.startswith("epoch") and (int(m.split()[1][:-1]) % 5 == 0) else None)
+        out["train"] = dict(samples=int(X.shape[0]), cold_cycles_median=float(np.median(train_cycles)),
+                            loss_first=losses[0], loss_last=losses[-1],
+                            prior_mse=float((T.astype(np.float64) ** 2).mean()),
+                            seconds_data=t_data, seconds_train=time.perf_counter() - t0)
+        out["loss_first"], out["loss_last"] = losses[0], losses[-1]
+        if save_net:
+            np.save(save_net, net.state())
+        log(f"[warmstart] data {t_data:.0f}s, training {out['train']['seconds_train']:.0f}s")
+    else:
+        net = load_net(net_params)
     results = {}
-    sw = workloads.sweep(seed=3000, n=test_sweep, target_sites=test_sweep_sites)
-    cmp = compare_starts(net, sw, dtype, max_cycles=max_cycles)
-    modes = ("cold", "prior", "warm")
-    results["sweep"] = dict(state_diff=cmp["state_diff"])
-    for m in modes:
-        results["sweep"][m] = cmp[m].cycles
-        results["sweep"][m + "_du"] = cmp[m].du
-        results["sweep"][m + "_dp"] = cmp[m].dp
-    log(f"[warmstart] sweep: cold {cmp['cold'].cycles} prior {cmp['prior'].cycles} "
-        f"warm {cmp['warm'].cycles}")
-    trees = dict(state_diff=[], sites=[])
-    for m in modes:
-        trees[m] = []
-        trees[m + "_du"] = []
-        trees[m + "_dp"] = []
-    for i in range(test_trees):
-        wl = workloads.tree(seed=2000 + i, scale=tree_scale)
-        cmp = compare_starts(net, wl, dtype, max_cycles=max_cycles, log=log)
-        for m in modes:
-            trees[m] += cmp[m].cycles
-            trees[m + "_du"] += cmp[m].du
-            trees[m + "_dp"] += cmp[m].dp
-        trees["state_diff"] += cmp["state_diff"]
-        trees["sites"].append(wl.n_sites)
-        log(f"[warmstart] tree {i}: {wl.n_sites} sites cold {cmp['cold'].cycles} "
-            f"prior {cmp['prior'].cycles} warm {cmp['warm'].cycles} "
-            f"diff {cmp['state_diff'][0]:.1e}")
-    results["trees"] = trees
-    cold = results["sweep"]["cold"] + trees["cold"]
-    warm = results["sweep"]["warm"] + trees["warm"]
-    pri = results["sweep"]["prior"] + trees["prior"]
-    ok = [(c, w) for c, w in zip(cold, warm) if c > 0 and w > 0]
-    return dict(
-        cycles_prior_mean=float(np.mean([x for x in pri if x > 0])) if pri else None,
-        cycles=dict(sweep={m: results["sweep"][m] for m in modes},
-                    trees={m: trees[m] for m in modes}),
-        config=dict(train_instances=train_batches * train_per_batch, train_sites_per_batch=train_sites,
-                    test_sweep=test_sweep, test_trees=test_trees, tree_scale=tree_scale, dtype=dtype,
-                    epochs=epochs, samples=int(X.shape[0]), tol=1e-3, period=int(workloads.PERIOD)),
-        train_cold_cycles_median=float(np.median(train_cycles)),
-        loss_first=losses[0], loss_last=losses[-1],
-        cycles_cold_mean=float(np.mean([c for c, _ in ok])) if ok else None,
-        cycles_warm_mean=float(np.mean([w for _, w in ok])) if ok else None,
-        median_ratio=float(np.median([w / c for c, w in ok])) if ok else None,
-        all_converged=len(ok) == len(cold),
-        max_state_diff=float(max(results["sweep"]["state_diff"] + trees["state_diff"])),
-        seconds=dict(data=t_data, train=t_train, total=time.perf_counter() - t_all),
-        results=results)
+    blank = lambda: dict(state_diff=[], sites=[], **{k: [] for m in MODES
+                                                      for k in (m, m + "_du", m + "_dp")})
+    if test_sweep:
+        results["sweep"] = blank()
+        sw = workloads.sweep(seed=3000, n=test_sweep, target_sites=test_sweep_sites)
+        cmp = _evaluate(net, sw, dtype, max_cycles, results["sweep"], log)
+        log("[warmstart] sweep: " + " ".join(f"{m} {cmp[m].cycles}" for m in MODES))
+    if test_trees:
+        results["trees"] = blank()
+        for i in range(tree_first, tree_first + test_trees):
+            t0 = time.perf_counter()
+            wl = workloads.tree(seed=2000 + i, scale=tree_scale)
+            cmp = _evaluate(net, wl, dtype, max_cycles, results["trees"], log)
+            log(f"[warmstart] tree {i}: {wl.n_sites} sites " +
+                " ".join(f"{m} {cmp[m].cycles}" for m in MODES) +
+                f" diff {cmp['state_diff'][0]:.1e}, {time.perf_counter() - t0:.0f}s")
+    out["results"] = results
+    out.update(summarize(results))
+    out["seconds_total"] = time.perf_counter() - t_all
+    return out, net
 
 
 def main(argv=None):
@@ -432,18 +689,35 @@ def main(argv=None):
     ap.add_argument("--test-sweep", type=int, default=16)
     ap.add_argument("--test-sweep-sites", type=float, default=5e6)
     ap.add_argument("--test-trees", type=int, default=16)
+    ap.add_argument("--tree-first", type=int, default=0)
     ap.add_argument("--tree-scale", type=float, default=1.0)
     ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--dtype", default="f32")
-    ap.add_argument("--out", default=None)
+    ap.add_argument("--save-net", default=None, help="write the trained parameters (.npy)")
+    ap.add_argument("--load-net", default=None, help="skip training, use these parameters")
+    ap.add_argument("--out", default=None, help="write the full result (JSON)")
+    ap.add_argument("--merge", nargs="+", default=None,
+                    help="only combine the per-instance results of earlier --out files")
     a = ap.parse_args(argv)
-    r = experiment(a.train_batches, a.train_per_batch, a.train_sites, a.test_sweep,
-                   a.test_sweep_sites, a.test_trees, a.tree_scale, a.dtype, a.epochs,
-                   log=lambda m: print(m, flush=True))
-    s = json.dumps(r)
+    if a.merge:
+        runs = [json.load(open(f)) for f in a.merge]
+        results = {}
+        for r in runs:
+            for name, g in r["results"].items():
+                tgt = results.setdefault(name, {k: [] for k in g})
+                for k, v in g.items():
+                    tgt[k] += v
+        r = dict(runs=a.merge, train=next((x["train"] for x in runs if "train" in x), None),
+                 results=results, **summarize(results))
+    else:
+        p = np.load(a.load_net) if a.load_net else None
+        r, net = experiment(a.train_batches, a.train_per_batch, a.train_sites, a.test_sweep,
+                            a.test_sweep_sites, a.test_trees, a.tree_first, a.tree_scale,
+                            a.dtype, a.epochs, net_params=p, save_net=a.save_net,
+                            log=lambda m: print(m, flush=True))
     if a.out:
         with open(a.out, "w") as f:
-            f.write(s + "\n")
+            f.write(json.dumps(r) + "\n")
     print(json.dumps({k: v for k, v in r.items() if k != "results"}), flush=True)
 
 

@@ -30,9 +30,9 @@ def test_init_fields_device_matches_host_init():
 
 def test_warm_start_reaches_the_cold_periodic_state_in_fewer_cycles():
     from paper_2108_08783_amd import warmstart
-    r = warmstart.experiment(train_batches=1, train_per_batch=16, train_sites=1.5e6,
-                             test_sweep=6, test_sweep_sites=6e5, test_trees=1, tree_scale=0.25,
-                             epochs=25, sites_per_phase=1024, log=print)
+    r, _ = warmstart.experiment(train_batches=1, train_per_batch=16, train_sites=1.5e6,
+                                test_sweep=6, test_sweep_sites=6e5, test_trees=1, tree_scale=0.25,
+                                epochs=25, sites_per_phase=1024, log=print)
     print({k: v for k, v in r.items() if k != "results"})
     assert r["all_converged"]
     assert r["loss_last"] < r["loss_first"] / 2

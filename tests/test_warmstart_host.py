@@ -1,0 +1,132 @@
+"""Host-side pieces of the learned warm start: the one-dimensional network
+prior against the limits it must reach (slip Poiseuille at low frequency, a
+lossless acoustic line for a full-slip wall, mass conservation, the slip
+condition itself) and the feature layout.  No GPU."""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate
+from scipy.special import jv
+
+from paper_2108_08783_amd import inputs, warmstart
+
+NU = 0.1
+
+
+@pytest.mark.parametrize("s", [0.0, 0.5, 0.85])
+def test_womersley_low_frequency_limit_is_slip_poiseuille(s):
+    # omega -> 0: the series impedance i omega / (pi r^2 m) must become the
+    # steady resistance 4 nu / (pi r^2 (b^2 - r^2/2)) of the slip parabola
+    r = 10.0
+    omega = 1e-7
+    kw = np.sqrt(-1j * omega / NU)
+    _, m = warmstart._womersley(r, s, kw)
+    Z = 1j * omega / (math.pi * r * r * m)
+    b2 = warmstart._b2(r, s)
+    R = 4 * NU / (math.pi * r * r * (b2 - 0.5 * r * r))
+    assert abs(Z - R) / R < 1e-4
+
+
+@pytest.mark.parametrize("r,s", [(6.0, 0.0), (20.0, 0.5), (40.0, 0.85)])
+def test_womersley_profile_meets_the_slip_condition_and_its_mean(r, s):
+    omega = 2 * math.pi / 4000
+    kw = np.sqrt(-1j * omega / NU)
+    beta, m = warmstart._womersley(r, s, kw)
+    prof = lambda y: 1.0 + beta * jv(0, kw * y)
+    Rw = r + 0.5
+    # slip rule: the wall node carries s times the velocity one node inside
+    assert abs(prof(Rw) - s * prof(Rw - 1.0)) < 1e-12 * max(1.0, abs(prof(Rw - 1.0)))
+    # the mean over the disk y < r, by quadrature
+    re = integrate.quad(lambda y: (prof(y) * 2 * y).real, 0, r, limit=200)[0] / (r * r)
+    im = integrate.quad(lambda y: (prof(y) * 2 * y).imag, 0, r, limit=200)[0] / (r * r)
+    assert abs(complex(re, im) - m) < 1e-9 * abs(m)
+
+
+def test_womersley_profile_satisfies_the_oscillating_momentum_equation():
+    # i omega u = -dp/dx + nu lap(u) with -dp/dx = i omega C0 (C0 = 1)
+    r, s = 15.0, 0.3
+    omega = 2 * math.pi / 4000
+    kw = np.sqrt(-1j * omega / NU)
+    beta, _ = warmstart._womersley(r, s, kw)
+    u = lambda y: 1.0 + beta * jv(0, kw * y)
+    for y in (1.0, 5.0, 12.0):
+        h = 1e-3
+        d2 = (u(y + h) - 2 * u(y) + u(y - h)) / h ** 2
+        d1 = (u(y + h) - u(y - h)) / (2 * h)
+        lap = d2 + d1 / y
+        assert abs(1j * omega * u(y) - (1j * omega + NU * lap)) < 1e-7
+
+
+def _tube(r=8.0, length=120.0):
+    g = inputs.straight_tube_x(r, length)
+    return g, warmstart.site_frames(g)
+
+
+def _section(fr, t0, t1):
+    t = fr.static[:, 3]
+    return (t > t0) & (t < t1)
+
+
+def test_prior_mean_flow_conserves_the_inlet_flow():
+    g, fr = _tube()
+    u0 = 0.02
+    P = warmstart.network_prior(g, fr, [1e9], 0.85, 1 / 3, u0, 0.0, nu=NU, amp=0.0)
+    r = 24.0 * fr.static[:, 1]
+    for lo in (0.2, 0.5, 0.8):
+        sel = _section(fr, lo, lo + 0.02)
+        # area-weighted mean axial velocity over the disk: the profile is
+        # normalised to mean 1 over y < r, so its site mean is close to 1
+        d = r[sel] * (1 - fr.static[sel, 0])
+        inside = d < r[sel] - 1
+        assert abs(P.Y[sel, 1][inside].mean() - 1.0) < 0.08
+
+
+def _excess_pressure(P, u0):
+    # output 0 is (3p - 1)/(10 u0), so p - 1/3 = out * 10 u0 / 3
+    return P.Y[:, 0] * 10 * u0 / 3
+
+
+def test_prior_low_frequency_is_quasi_steady():
+    # period -> infinity: at a quarter period (flow 1 + amp times the mean)
+    # pressure excess and velocity are the steady ones scaled by 1 + amp
+    g, fr = _tube()
+    u0, amp = 0.02, 0.5
+    k = [1e9]                                   # stiff: constant slip F
+    base = warmstart.network_prior(g, fr, k, 0.85, 1 / 3, u0, 0.0, nu=NU, amp=0.0, period=1e9)
+    peak = warmstart.network_prior(g, fr, k, 0.85, 1 / 3, u0, 0.25, nu=NU, amp=amp, period=1e9)
+    dps, dpp = _excess_pressure(base, u0), _excess_pressure(peak, u0)
+    sel = dps > 0.2 * dps.max()
+    assert np.allclose(dpp[sel], (1 + amp) * dps[sel], rtol=1e-4)
+    assert np.allclose(peak.Y[:, 1], (1 + amp) * base.Y[:, 1], rtol=1e-4, atol=1e-6)
+
+
+def test_prior_full_slip_line_is_a_lossless_acoustic_line():
+    # F = 1 (slip factor 1, plug flow, no viscous drop): an inviscid line
+    # with wave speed c = 1/sqrt(3), flow amplitude -i amp A u0 at x = 0 and
+    # p = P0 at x = L has the pressure phasor
+    #   p(x) - P0 = c amp u0 sin(w (L - x)/c) / cos(w L/c)   (real)
+    g, fr = _tube(r=8.0, length=100.0)
+    seg = g.segments[0]
+    L = float(np.linalg.norm(seg.p1 - seg.p0))
+    c = 1 / math.sqrt(3)
+    omega = c * (math.pi / 4) / L
+    u0, amp = 0.02, 0.5
+    kw = dict(nu=NU, amp=amp, period=2 * math.pi / omega, n_sub=64)
+    p0 = warmstart.network_prior(g, fr, [1e9], 1.0, 1 / 3, u0, 0.0, **kw)
+    p1 = warmstart.network_prior(g, fr, [1e9], 1.0, 1 / 3, u0, 0.25, **kw)
+    x = fr.static[:, 3] * L
+    want = c * amp * u0 * np.sin(omega * (L - x) / c) / math.cos(omega * L / c)
+    assert np.abs(_excess_pressure(p0, u0) - want).max() < 1e-3 * want.max()
+    assert np.abs(_excess_pressure(p1, u0)).max() < 1e-3 * want.max()
+
+
+def test_feature_layout():
+    g, fr = _tube()
+    P = warmstart.network_prior(g, fr, [0.01], 0.5, 1 / 3, 0.02, 0.1, nu=NU)
+    X = warmstart.features(fr, [0.01], 0.02, 0.1, P)
+    assert X.shape == (fr.static.shape[0], warmstart.N_FEAT)
+    assert np.array_equal(X[:, 5], P.Y[:, 0]) and np.array_equal(X[:, 10], P.Y[:, 1])
+    assert np.array_equal(X[:, 11], P.slip)
+    assert np.all(X[:, 7] == 1.0) and np.all(X[:, 8:10] == 0.0)     # one generation-0 tube
+    assert np.allclose(X[:, 14], math.sin(0.2 * math.pi)) and np.allclose(X[:, 15], math.cos(0.2 * math.pi))
