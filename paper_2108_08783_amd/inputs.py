@@ -242,7 +242,8 @@ def voxelise(segments: List[Segment], shape, iolet_of_segment=None) -> Geometry:
         cap = (ax > L) & (ax <= L + 1.8) & (rad2 < (s.r1 + 1.8) ** 2)
         sub = lab[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]]
         sub[cap] = IOLET0 + io
-        iolets.append(dict(id=io, role="outlet", direction=tuple(-d / L), segment=s.sid))
+        iolets.append(dict(id=io, role="outlet", direction=tuple(-d / L), segment=s.sid,
+                           box=(lo, hi)))
     for s in segments:
         r_max = max(s.r0, s.r1)
         lo, hi = bbox([s.p0, s.p1], r_max + 2)
@@ -276,10 +277,40 @@ def voxelise(segments: List[Segment], shape, iolet_of_segment=None) -> Geometry:
             iolets.insert(0, dict(id=0, role="inlet", direction=tuple((s.p1 - s.p0) /
                                                                       np.linalg.norm(s.p1 - s.p0))))
     _resolve_iolet_conflicts(lab)
+    # an outlet whose cap lost every voxel next to fluid to another iolet is
+    # closed: drop it from the list and from its segment
+    segments = list(segments)
+    kept = []
+    for io in iolets:
+        if io["role"] == "outlet":
+            lo, hi = io.pop("box")
+            if not _touches_fluid(lab, IOLET0 + io["id"], lo, hi):
+                k = next(i for i, q in enumerate(segments) if q.sid == io["segment"])
+                segments[k] = dataclasses.replace(segments[k], outlet=False)
+                continue
+        kept.append(io)
     g = Geometry(labels=lab, segment=seg, iolet_weight=iw, n_seg=len(segments))
-    g.iolets = iolets
-    g.segments = list(segments)
+    g.iolets = kept
+    g.segments = segments
     return g
+
+
+def _touches_fluid(lab, code, lo, hi):
+    """Whether a voxel labelled `code` inside the box [lo, hi) (x, y, z
+    order) has a fluid voxel among its 18 neighbours."""
+    nz, ny, nx = lab.shape
+    z0, y0, x0 = max(lo[2] - 1, 0), max(lo[1] - 1, 0), max(lo[0] - 1, 0)
+    z1, y1, x1 = min(hi[2] + 1, nz), min(hi[1] + 1, ny), min(hi[0] + 1, nx)
+    sub = lab[z0:z1, y0:y1, x0:x1]
+    mine = sub == code
+    if not mine.any():
+        return False
+    fl = np.pad(sub == FLUID, 1)
+    Z, Y, X = sub.shape
+    for dx, dy, dz in _OFFS18:
+        if (mine & fl[1 + dz:1 + dz + Z, 1 + dy:1 + dy + Y, 1 + dx:1 + dx + X]).any():
+            return True
+    return False
 
 
 _OFFS18 = [(dx, dy, dz) for dx in (-1, 0, 1) for dy in (-1, 0, 1) for dz in (-1, 0, 1)

@@ -237,17 +237,24 @@ def network_prior(geo: inputs.Geometry, frame: SiteFrame, k_seg, F: float, P0: f
     Q0 = math.pi * r_in * r_in * u0
 
     # ---- mean flow: pressures from the outlets up, flow split by resistance
+    # (a subtree without an outlet carries no mean flow)
+    opened = [False] * n
+    for i in range(n - 1, -1, -1):
+        opened[i] = segs[i].outlet or any(opened[c] for c in children[i])
+    kids = [[c for c in children[i] if opened[c]] for i in range(n)]
     Q = np.zeros(n)
     Q[0] = Q0
     for i in range(n):                       # Murray split to start
-        if children[i]:
-            w = np.array([segs[c].r0 ** 3 for c in children[i]])
-            Q[children[i]] = Q[i] * w / w.sum()
+        if kids[i]:
+            w = np.array([segs[c].r0 ** 3 for c in kids[i]])
+            Q[kids[i]] = Q[i] * w / w.sum()
     pst = np.zeros((n, n_sub + 1))
     slp = np.zeros((n, n_sub))
     for _ in range(iters):
         for i in range(n - 1, -1, -1):
-            p = P0 if not children[i] else float(np.mean([pst[c, 0] for c in children[i]]))
+            if not opened[i]:
+                continue
+            p = P0 if not kids[i] else float(np.mean([pst[c, 0] for c in kids[i]]))
             pst[i, n_sub] = p
             for m in range(n_sub - 1, -1, -1):
                 sl = float(_slip(p, k[i], F, P0))
@@ -259,12 +266,16 @@ def network_prior(geo: inputs.Geometry, frame: SiteFrame, k_seg, F: float, P0: f
         Rseg = (pst[:, 0] - pst[:, n_sub]) / np.maximum(Q, 1e-30)
         Req = np.zeros(n)
         for i in range(n - 1, -1, -1):
-            down = 1.0 / sum(1.0 / Req[c] for c in children[i]) if children[i] else 0.0
+            down = 1.0 / sum(1.0 / Req[c] for c in kids[i]) if kids[i] else 0.0
             Req[i] = Rseg[i] + down
         for i in range(n):
-            if children[i]:
-                g = np.array([1.0 / Req[c] for c in children[i]])
-                Q[children[i]] = Q[i] * g / g.sum()
+            if kids[i]:
+                g = np.array([1.0 / Req[c] for c in kids[i]])
+                Q[kids[i]] = Q[i] * g / g.sum()
+    for i in range(n):                       # dead ends: the junction's pressure
+        if not opened[i] and parent[i] >= 0:
+            pst[i, :] = pst[parent[i], n_sub]
+            slp[i, :] = _slip(pst[i, 0], k[i], F, P0)
 
     # ---- oscillating flow at the drive frequency
     beta, mfac = _womersley(rp, slp, kw)
@@ -613,14 +624,15 @@ def summarize(results):
 def experiment(train_batches=4, train_per_batch=64, train_sites=20e6, test_sweep=16,
                test_sweep_sites=5e6, test_trees=16, tree_first=0, tree_scale=1.0, dtype="f32",
                epochs=30, sites_per_phase=2048, max_cycles=12, seed=0, net_params=None,
-               save_net=None, log=print):
+               save_net=None, checkpoint=None, log=print):
     """Train on cold-started sweep batches (seeds 1000.., run to
     periodicity, sampled at 8 phases) unless `net_params` is given, then
     start held-out sweep instances (seed 3000) and Murray trees (seeds
     2000 + tree_first ..) cold, from the prior and from the network, and
     run each to periodicity.  The trained parameters are written to
-    `save_net` (.npy) before the evaluation starts.  Returns (JSON-ready
-    dict, network)."""
+    `save_net` (.npy) before the evaluation starts; `checkpoint(dict)` is
+    called with the results so far after each evaluated workload.  Returns
+    (JSON-ready dict, network)."""
     t_all = time.perf_counter()
     out = dict(config=dict(train_instances=train_batches * train_per_batch,
                            train_sites_per_batch=train_sites, test_sweep=test_sweep,
@@ -664,6 +676,8 @@ def experiment(train_batches=4, train_per_batch=64, train_sites=20e6, test_sweep
         sw = workloads.sweep(seed=3000, n=test_sweep, target_sites=test_sweep_sites)
         cmp = _evaluate(net, sw, dtype, max_cycles, results["sweep"], log)
         log("[warmstart] sweep: " + " ".join(f"{m} {cmp[m].cycles}" for m in MODES))
+        if checkpoint:
+            checkpoint(dict(out, results=results, **summarize(results)))
     if test_trees:
         results["trees"] = blank()
         for i in range(tree_first, tree_first + test_trees):
@@ -673,6 +687,8 @@ def experiment(train_batches=4, train_per_batch=64, train_sites=20e6, test_sweep
             log(f"[warmstart] tree {i}: {wl.n_sites} sites " +
                 " ".join(f"{m} {cmp[m].cycles}" for m in MODES) +
                 f" diff {cmp['state_diff'][0]:.1e}, {time.perf_counter() - t0:.0f}s")
+            if checkpoint:
+                checkpoint(dict(out, results=results, **summarize(results)))
     out["results"] = results
     out.update(summarize(results))
     out["seconds_total"] = time.perf_counter() - t_all
@@ -711,10 +727,14 @@ def main(argv=None):
                  results=results, **summarize(results))
     else:
         p = np.load(a.load_net) if a.load_net else None
+        def save(d):
+            if a.out:
+                with open(a.out, "w") as f:
+                    f.write(json.dumps(d) + "\n")
         r, net = experiment(a.train_batches, a.train_per_batch, a.train_sites, a.test_sweep,
                             a.test_sweep_sites, a.test_trees, a.tree_first, a.tree_scale,
                             a.dtype, a.epochs, net_params=p, save_net=a.save_net,
-                            log=lambda m: print(m, flush=True))
+                            checkpoint=save, log=lambda m: print(m, flush=True))
     if a.out:
         with open(a.out, "w") as f:
             f.write(json.dumps(r) + "\n")
