@@ -29,8 +29,9 @@ frame (axial, radial, azimuthal), each as a correction to a physics prior
 (`network_prior`): a linear one-dimensional model of the segment tree with
 slip-Poiseuille mean flow and, at the drive frequency, a transmission line
 per segment with the slip Womersley impedance and the lattice's
-compressibility.  Sites unlike the training data fall back toward the
-prior.
+compressibility.  The correction is applied only at sites whose features
+all lie inside the range seen in training (with a 5 % margin); elsewhere
+the start is the prior.
 """
 from __future__ import annotations
 
@@ -471,12 +472,29 @@ def new_net(seed=0, width=128, depth=4):
     return mlp.Net(N_FEAT, width, depth, N_OUT, params=p)
 
 
+def feature_range(X: np.ndarray, margin: float = 0.05) -> np.ndarray:
+    """[2, N_FEAT] bounds of the training features, widened by `margin` of
+    each feature's span (features constant in training stay exact)."""
+    lo, hi = X.min(0).astype(np.float64), X.max(0).astype(np.float64)
+    pad = margin * (hi - lo)
+    return np.stack([lo - pad, hi + pad])
+
+
+def in_range(X: np.ndarray, rng: Optional[np.ndarray]) -> np.ndarray:
+    """Per site: every feature inside the training range."""
+    if rng is None:
+        return np.ones(X.shape[0], bool)
+    return np.all((X >= rng[0]) & (X <= rng[1]), axis=1)
+
+
 def train(net, X: np.ndarray, T: np.ndarray, epochs=30, batch=8192, lr=2e-3, seed=0,
           weights=(1.0, 1.0, 1.0, 1.0), log=None):
-    """Adam on the weighted MSE with a cosine learning-rate decay; returns
-    the per-epoch mean losses."""
+    """Adam on the weighted MSE with a cosine learning-rate decay; records
+    the training features' range on the network (`feature_range`);
+    returns the per-epoch mean losses."""
     import torch
     rng = np.random.default_rng(seed)
+    net.feature_range = feature_range(X)
     Xt = net.to_bf16(torch.tensor(X, dtype=torch.float32, device="cuda"))
     Tt = torch.tensor(T, dtype=torch.float32, device="cuda")
     w = torch.tensor(weights, dtype=torch.float32, device="cuda")
@@ -508,18 +526,22 @@ def instance_prior(geo, frame: SiteFrame, params, phase, nu=0.1) -> Prior:
 def predict(net, geo, frame: SiteFrame, params, phase, nu=0.1, chunk=1 << 20, use_net=True,
             prior: Optional[Prior] = None):
     """(rho, u) of every site of one instance: the network prior plus the
-    network's correction (clipped to the trust region)."""
+    network's correction (clipped to the trust region, only at sites whose
+    features lie inside the training range)."""
     import torch
     u0 = params.iolets[0]["a0"]
     pr = prior if prior is not None else instance_prior(geo, frame, params, phase, nu)
     Y = pr.Y.copy()
     if use_net:
         X = features(frame, params.k, u0, phase, pr)
+        ok = in_range(X, getattr(net, "feature_range", None))
         for s in range(0, X.shape[0], chunk):
             xb = net.to_bf16(torch.tensor(X[s:s + chunk], device="cuda"))
             # trust region: the correction to the prior is at most one output
-            # unit (u0 in velocity, 10 u0 in density)
-            Y[s:s + chunk] += np.clip(net.forward(xb).cpu().numpy(), -TRUST, TRUST)
+            # unit (u0 in velocity, 10 u0 in density), and none at sites
+            # whose features lie outside the training range
+            dY = np.clip(net.forward(xb).cpu().numpy(), -TRUST, TRUST)
+            Y[s:s + chunk] += dY * ok[s:s + chunk, None]
     return assemble(frame, Y, u0)
 
 
@@ -576,10 +598,20 @@ def compare_starts(net, wl: workloads.Workload, dtype="f32", tol=1e-3, max_cycle
 MODES = ("cold", "prior", "warm")
 
 
-def load_net(params):
-    """Network with the standard shape and the given parameters."""
+def save_net_file(path, net):
+    """Parameters and training-feature range of a network (.npz)."""
+    np.savez(path, params=net.state(), feature_range=net.feature_range)
+
+
+def load_net(state):
+    """Network with the standard shape from `save_net_file`'s contents (a
+    mapping with params and feature_range) or a bare parameter vector."""
     from . import mlp
-    return mlp.Net(N_FEAT, 128, 4, N_OUT, params=np.asarray(params, np.float64))
+    if hasattr(state, "keys"):
+        net = mlp.Net(N_FEAT, 128, 4, N_OUT, params=np.asarray(state["params"], np.float64))
+        net.feature_range = np.asarray(state["feature_range"], np.float64)
+        return net
+    return mlp.Net(N_FEAT, 128, 4, N_OUT, params=np.asarray(state, np.float64))
 
 
 def _evaluate(net, wl, dtype, max_cycles, group, log):
@@ -630,7 +662,7 @@ def experiment(train_batches=4, train_per_batch=64, train_sites=20e6, test_sweep
     start held-out sweep instances (seed 3000) and Murray trees (seeds
     2000 + tree_first ..) cold, from the prior and from the network, and
     run each to periodicity.  The trained parameters are written to
-    `save_net` (.npy) before the evaluation starts; `checkpoint(dict)` is
+    `save_net` (.npz) before the evaluation starts; `checkpoint(dict)` is
     called with the results so far after each evaluated workload.  Returns
     (JSON-ready dict, network)."""
     t_all = time.perf_counter()
@@ -664,7 +696,7 @@ def experiment(train_batches=4, train_per_batch=64, train_sites=20e6, test_sweep
                             seconds_data=t_data, seconds_train=time.perf_counter() - t0)
         out["loss_first"], out["loss_last"] = losses[0], losses[-1]
         if save_net:
-            np.save(save_net, net.state())
+            save_net_file(save_net, net)
         log(f"[warmstart] data {t_data:.0f}s, training {out['train']['seconds_train']:.0f}s")
     else:
         net = load_net(net_params)
@@ -709,7 +741,8 @@ def main(argv=None):
     ap.add_argument("--tree-scale", type=float, default=1.0)
     ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--dtype", default="f32")
-    ap.add_argument("--save-net", default=None, help="write the trained parameters (.npy)")
+    ap.add_argument("--save-net", default=None,
+                    help="write the trained parameters and feature range (.npz)")
     ap.add_argument("--load-net", default=None, help="skip training, use these parameters")
     ap.add_argument("--out", default=None, help="write the full result (JSON)")
     ap.add_argument("--merge", nargs="+", default=None,
@@ -726,7 +759,7 @@ def main(argv=None):
         r = dict(runs=a.merge, train=next((x["train"] for x in runs if "train" in x), None),
                  results=results, **summarize(results))
     else:
-        p = np.load(a.load_net) if a.load_net else None
+        p = dict(np.load(a.load_net)) if a.load_net else None
         def save(d):
             if a.out:
                 with open(a.out, "w") as f:

@@ -130,3 +130,17 @@ def test_feature_layout():
     assert np.array_equal(X[:, 11], P.slip)
     assert np.all(X[:, 7] == 1.0) and np.all(X[:, 8:10] == 0.0)     # one generation-0 tube
     assert np.allclose(X[:, 14], math.sin(0.2 * math.pi)) and np.allclose(X[:, 15], math.cos(0.2 * math.pi))
+
+
+def test_feature_range_gate():
+    rng = np.random.default_rng(0)
+    X = rng.uniform(0, 1, (1000, warmstart.N_FEAT)).astype(np.float32)
+    X[:, 9] = 0.0                                   # a slot never set in training
+    r = warmstart.feature_range(X)
+    assert warmstart.in_range(X, r).all()
+    Y = X[:5].copy()
+    Y[0, 3] = 1.2                                   # beyond the 5 % margin
+    Y[1, 3] = 1.04                                  # inside it
+    Y[2, 9] = 1.0                                   # the unseen slot
+    assert warmstart.in_range(Y, r).tolist() == [False, True, False, True, True]
+    assert warmstart.in_range(Y, None).all()
