@@ -294,3 +294,114 @@ def test_elastic_extension_clamp_and_monotonicity():
     assert res["soft"][1][:, 2].sum() > res["inf"][1][:, 2].sum() * 1.01
     dr = res["soft"][3]
     assert dr.max() > 1.0 and np.all((dr == 0) | (dr >= 1.0))
+
+
+# ------------------------------------------------- Womersley (P7) --------
+def test_womersley_closed_forms_reduce_to_known_cases():
+    """The series Bessel function against SciPy's, and both Womersley
+    profiles against their Poiseuille limits as omega -> 0 and their no-slip
+    and momentum equations at finite omega."""
+    from scipy.special import jv
+    for z in (0.3 + 0.1j, 2.0 * np.exp(0.75j * np.pi), 3.0 * np.exp(0.75j * np.pi), 4.2 - 1.0j):
+        for n in (0, 1):
+            assert abs(cf.bessel_j(n, z) - jv(n, z)) <= 1e-12 * max(1.0, abs(jv(n, z)))
+    nu, rho, G = 0.1, 1.0, 1e-5
+    # omega -> 0: Poiseuille (the i omega in the prefactor cancels)
+    om = 1e-9
+    y = np.linspace(-3.9, 3.9, 9)
+    up = cf.womersley_plane(y, 4.0, nu, G, rho, om)
+    assert np.allclose(up.real, cf.plane_poiseuille(y, 4.0, G, rho * nu), rtol=1e-6)
+    r = np.linspace(0.0, 5.9, 7)
+    alpha = 6.0 * math.sqrt(om / nu)
+    ur = cf.womersley_pipe(r, 6.0, alpha, G, rho, om)
+    assert np.allclose(ur.real, G / (4 * rho * nu) * (36.0 - r ** 2), rtol=1e-5)
+    # finite omega: zero at the wall and i omega u = G/rho + nu u''
+    om = 2 * math.pi / 1000
+    h = 8.0
+    assert abs(cf.womersley_plane([h], h, nu, G, rho, om)[0]) < 1e-15
+    for yy in (0.0, 3.0, 6.5):
+        e = 1e-3
+        u0, um, upp = (cf.womersley_plane([yy + d], h, nu, G, rho, om)[0] for d in (0.0, -e, e))
+        lhs = 1j * om * u0
+        rhs = G / rho + nu * (upp - 2 * u0 + um) / e ** 2
+        assert abs(lhs - rhs) < 1e-6 * abs(G / rho)
+    R = 12.0
+    alpha = R * math.sqrt(om / nu)
+    assert abs(cf.womersley_pipe([R], R, alpha, G, rho, om)[0]) < 1e-14
+    for rr in (2.0, 6.0, 10.0):
+        e = 1e-3
+        u0, um, upp = (cf.womersley_pipe([rr + d], R, alpha, G, rho, om)[0] for d in (0.0, -e, e))
+        lap = (upp - 2 * u0 + um) / e ** 2 + (upp - um) / (2 * e) / rr
+        assert abs(1j * om * u0 - (G / rho + nu * lap)) < 1e-6 * abs(G / rho)
+
+
+def _oscillating(geo, tau, period, amp, periods=3, stride=5):
+    """Density iolets 1 +- amp sin(2 pi t / period) at the two ends; after
+    `periods` periods, returns the first Fourier coefficients over one more
+    period of the mid-section pressure gradient -dp/dz (section means) and
+    of u_z at every site of the mid-section, with the site coordinates."""
+    o = oracle.Oracle(geo.labels, tau)
+    o.set_wall(0)
+    o.set_iolet(0, 0, 1.0, amp, period, 0.0)
+    o.set_iolet(1, 0, 1.0, amp, period, math.pi)
+    o.init_fields()
+    o.step(periods * period)
+    xyz = o.coords()
+    zc = int(np.median(xyz[:, 2]))
+    mid, up, dn = (xyz[:, 2] == zc), (xyz[:, 2] == zc + 1), (xyz[:, 2] == zc - 1)
+    omega = 2 * math.pi / period
+    Gh, uh, n = 0j, 0j, 0
+    for _ in range(period // stride):
+        rho, u, _, _ = o.read()
+        e = np.exp(-1j * omega * o.time)
+        Gh = Gh + (-(rho[up].mean() - rho[dn].mean()) / 6.0) * e
+        uh = uh + u[mid, 2] * e
+        n += 1
+        o.step(stride)
+    return 2 * Gh / n, 2 * uh / n, xyz[mid], omega, rho[mid].mean()
+
+
+@pytest.mark.slow
+def test_womersley_plane_channel():
+    """P7: oscillating density drop between bounce-back plates (the centre
+    plane of a wide duct) at Womersley number 2; the mid-section profile's
+    complex amplitude follows the plane Womersley solution for the measured
+    local gradient, converging about second order in the plate spacing."""
+    errs = []
+    for H in (8, 16):
+        g = inputs.duct(4 * H, H, 4 * H)
+        nu = 0.1
+        # omega from Womersley number 2 on the half-width H/2
+        period = int(round(2 * math.pi / (nu * (2.0 / (H / 2)) ** 2)))
+        Gh, uh, xyz, om, rho = _oscillating(g, 0.8, period, 2e-4)
+        sel = xyz[:, 0] == 2 * H
+        y = xyz[sel, 1] - (H + 1) / 2
+        ua = cf.womersley_plane(y, H / 2, nu, Gh, rho, om)
+        errs.append(np.abs(uh[sel] - ua).max() / np.abs(ua).max())
+    assert errs[1] <= 0.02
+    assert errs[0] / errs[1] > 2.5
+
+
+@pytest.mark.slow
+def test_womersley_rigid_pipe():
+    """P7: the paper's rigid-tube limit (Sec. 2.2 with M = 1) at its
+    Womersley number 3: a bounce-back cylinder of radius 16 with an
+    oscillating density drop.  The staircase wall is taken at the radius of
+    the disk with the section's area; every mid-section site's complex
+    amplitude is within 5 % (rms 2 %) of the pipe Womersley solution for
+    the measured gradient."""
+    R, nu = 16, 0.1
+    g = inputs.cylinder(R, 4 * R)
+    n_section = int((g.labels[g.labels.shape[0] // 2] == inputs.FLUID).sum())
+    R_eff = math.sqrt(n_section / math.pi)
+    period = 5 * int(round(2 * math.pi / (nu * (3.0 / R_eff) ** 2) / 5))
+    Gh, uh, xyz, om, rho = _oscillating(g, 0.8, period, 2e-4)
+    c = (np.array(g.labels.shape[::-1]) - 1) / 2.0
+    r = np.hypot(xyz[:, 0] - c[0], xyz[:, 1] - c[1])
+    assert len(r) == n_section
+    alpha = R_eff * math.sqrt(om / nu)
+    assert alpha == pytest.approx(3.0, rel=0.01)
+    ua = cf.womersley_pipe(r, R_eff, alpha, Gh, rho, om)
+    err = np.abs(uh - ua) / np.abs(ua).max()
+    assert err.max() <= 0.05
+    assert np.sqrt((err ** 2).mean()) <= 0.02
