@@ -216,25 +216,31 @@ def test_cycle_delta_monitor():
     lat.close()
 
 
-def test_full_size_tube_parity_short_run():
+def test_full_size_tube_parity():
     """The 1,640,960-site tube (R=32, L=512) in the benchmark's launch
-    configuration (autotuned), from a non-equilibrium state, 24 steps, FP32
-    against the oracle over every site."""
+    configuration (autotuned), from a non-equilibrium state, 1000 steps,
+    against one oracle run over every site: FP32 within 1e-5 on u and p;
+    FP16 and BF16 storage stated (bounded loosely)."""
     p = H.tube_problem(32, 512, seed=1, period=4000.0)
     rng = np.random.default_rng(12)
     n = p.geo.n_fluid
     p.u0 = np.zeros((n, 3))
     p.u0[:, 2] = 0.02 + 0.002 * rng.uniform(-1, 1, n)
     p.rho0 = 1 + 1e-3 * rng.uniform(-1, 1, n)
-    lat = H.make_lattice([p], "f32")
-    lat.autotune(16)
-    lat.step(24)
+    steps = 1000
     o = H.make_oracle(p)
-    o.step(24)
-    e = H.errors(lat.read_fields(0), o.read(), P0=p.P0)
-    record("tube32_full_size", e, dtype="f32", steps=24, launch=lat.info())
-    assert e["u"] <= 1e-5 and e["p"] <= 1e-5
-    lat.close()
+    o.step(steps)
+    ref = o.read()
+    bound = {"f32": (1e-5, 1e-5), "f16": (5e-3, 5e-3), "bf16": (5e-2, 5e-2)}
+    for dtype in ("f32", "f16", "bf16"):
+        lat = H.make_lattice([p], dtype)
+        lat.autotune(16)
+        lat.step(steps)
+        e = H.errors(lat.read_fields(0), ref, P0=p.P0)
+        record("tube32_full_size", e, dtype=dtype, steps=steps, launch=lat.info())
+        print(dtype, e, flush=True)
+        assert e["u"] <= bound[dtype][0] and e["p"] <= bound[dtype][1], dtype
+        lat.close()
 
 
 def _tree_problem(scale, seed=3):
