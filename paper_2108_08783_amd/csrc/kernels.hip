@@ -308,18 +308,42 @@ __device__ __forceinline__ int remap_xcd(int b, int nblk) {
 //     Delta E = max(0, (p - P0) / k), p = rho / 3;
 //   density iolet (Sec. 3): rho' = rho_io(t), U' = u;
 //   velocity iolet (Sec. 3): rho' = rho, U' = weight(x) u_io(t) dir.
+// The parts of a boundary record the link rules read.
+template <typename acc>
+struct BRec {
+    uint32_t bw = 0, bi = 0;   // wall mask | instance, iolet mask | slot
+    acc c1 = 0, c0 = 0, F = 0; // elastic-wall coefficients (WallCoef)
+};
+
+template <typename acc>
+__device__ __forceinline__ BRec<acc> load_brec(const StepArgs& a, int j) {
+    BRec<acc> r;
+    r.bw = a.bwall[j];
+    r.bi = a.bio[j];
+    const WallCoef q = a.bq[j];
+    r.c1 = (acc)q.c1;
+    r.c0 = (acc)q.c0;
+    r.F = (acc)q.F;
+    return r;
+}
+
+// With 32- and 64-bit storage the record is loaded before the gathers, so
+// its latency overlaps theirs; 16-bit storage has no registers to spare at 8
+// waves per SIMD and loads it where it is used.
+template <int DT>
+constexpr bool hoist_records() { return !(DT == LBM_F16DEV || DT == LBM_BF16DEV); }
+
 template <typename acc>
 __device__ __forceinline__ void apply_links(const StepArgs& a, int j, const Mom<acc>& m,
-                                            acc (&out)[Q]) {
-    const uint32_t bw = a.bwall[j], bi = a.bio[j];
+                                            acc (&out)[Q], const BRec<acc>& r) {
+    const uint32_t bw = r.bw, bi = r.bi;
     const uint32_t wmask = bw & 0x7FFFEu, imask = bi & 0x7FFFEu;
     const uint32_t inst = bw >> 19;
     acc s = 0;
     if (wmask) {
-        const InstParams& P = a.ip[inst];
-        acc dE = (m.drho * (acc)(1.0 / 3.0) + (acc)P.dp0) * (acc)a.kinv[a.bk[j]];
+        acc dE = m.drho * r.c1 + r.c0;
         dE = dE > (acc)0 ? dE : (acc)0;
-        s = ((acc)P.F + dE) / ((acc)1 + dE);
+        s = (r.F + dE) / ((acc)1 + dE);
     }
     acc idr = m.drho, ir = m.rho, ix = m.ux, iy = m.uy, iz = m.uz;
     if (imask) {
@@ -372,7 +396,8 @@ __device__ __forceinline__ void apply_links(const StepArgs& a, int j, const Mom<
 // gathered (moments, BGK, link rules, 19 coalesced stores).
 template <int DT, bool SMALL>
 __device__ __forceinline__ void collide_store(const StepArgs& a, int x, bool ghost, int rec,
-                                              typename Codec<DT>::acc (&h)[Q]) {
+                                              typename Codec<DT>::acc (&h)[Q],
+                                              BRec<typename Codec<DT>::acc> br) {
     using raw = typename Codec<DT>::raw;
     using acc = typename Codec<DT>::acc;
     raw* __restrict__ B = (raw*)a.B;
@@ -385,7 +410,10 @@ __device__ __forceinline__ void collide_store(const StepArgs& a, int x, bool gho
         for (int i = 0; i < Q; ++i) h[i] = h[i] + om * (e[i] - h[i]);
     }
     acc (&out)[Q] = h;
-    if (ghost) apply_links<acc>(a, rec, m, out);
+    if (ghost) {
+        if constexpr (!hoist_records<DT>()) br = load_brec<acc>(a, rec);
+        apply_links<acc>(a, rec, m, out, br);
+    }
     const bool nt = (a.nontemporal & 1) != 0;
     using O = Off<DT, SMALL>;
     using T = typename O::type;
@@ -410,9 +438,12 @@ __device__ __forceinline__ void update_site(const StepArgs& a, int x, bool from_
 #pragma unroll
     for (int i = 0; i < 18; ++i) ghost |= (d[i] == Sentinel<int32_t>::GHOST);
     if (ghost && !from_boundary_blocks && !a.fused) return;
+    BRec<acc> br;
+    if constexpr (hoist_records<DT>())
+        if (ghost) br = load_brec<acc>(a, rec);
     acc h[Q];
     gather32<DT, SMALL, NTL>((const typename Codec<DT>::raw*)a.A, a.np, x, d, h);
-    collide_store<DT, SMALL>(a, x, ghost, rec, h);
+    collide_store<DT, SMALL>(a, x, ghost, rec, h, br);
 }
 
 // 16-bit storage is latency-bound: 8 waves per SIMD (at the cost of a few

@@ -27,6 +27,13 @@ struct IoletParams {
     int32_t pad;
 };
 
+// Elastic-wall coefficients of one boundary record (Sec. 2.3, 2.4): with
+// drho = rho - 1, Delta E = max(0, drho c1 + c0) and s = (F + Delta E) /
+// (1 + Delta E); c1 = 1/(3k), c0 = (1/3 - P0)/k of the site's segment.
+struct WallCoef {
+    double c1, c0, F, pad;
+};
+
 struct StepArgs {
     const void* A;          // populations read (deviation f - w, SoA, plane stride np)
     void* B;                // populations written
@@ -46,11 +53,10 @@ struct StepArgs {
     const int32_t* bidx;    // per site: record id, -1 for interior sites (table addressing)
     const uint32_t* bwall;  // elastic wall link mask | inst << 19
     const uint32_t* bio;    // iolet link mask | iolet slot << 19
-    const int32_t* bk;      // stiffness index
+    const WallCoef* bq;     // elastic-wall coefficients per record
     const float* bw;        // iolet profile weight
     const InstParams* ip;
     const IoletParams* iop;
-    const double* kinv;     // 1 / k per stiffness index
     int64_t* clock;         // [2] steps executed before the current one
     // compressed addressing (see Compressed in builder.hpp)
     const WfRec* wf;         // one record per 64 sites

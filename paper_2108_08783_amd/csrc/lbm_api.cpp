@@ -80,6 +80,8 @@ struct lbm_ctx {
     uint32_t* bwall = nullptr;
     uint32_t* bio = nullptr;
     int32_t* bk = nullptr;
+    WallCoef* bq = nullptr;
+    std::vector<int32_t> rec_k, rec_inst;  // per record: stiffness index, instance
     float* bw = nullptr;
     int64_t nb = 0, n_irr = 0;
     // compressed addressing
@@ -249,6 +251,19 @@ int sync_params(lbm_ctx* c) {
     int rc = upload(c, c->ip, ip.data(), ip.size() * sizeof(InstParams));
     rc = rc ? rc : upload(c, c->iop, iop.data(), iop.size() * sizeof(IoletParams));
     rc = rc ? rc : upload(c, c->kinv, kinv.data(), kinv.size() * sizeof(double));
+    {
+        // elastic-wall coefficients per boundary record
+        std::vector<WallCoef> bq(std::max<size_t>(1, c->rec_k.size()));
+        for (size_t j = 0; j < c->rec_k.size(); ++j) {
+            const InstState& s = c->ist[c->rec_inst[j]];
+            const double ki = kinv[c->rec_k[j]];
+            bq[j].c1 = ki / 3.0;
+            bq[j].c0 = (1.0 / 3.0 - s.P0) * ki;
+            bq[j].F = s.F;
+            bq[j].pad = 0.0;
+        }
+        rc = rc ? rc : upload(c, c->bq, bq.data(), c->rec_k.size() * sizeof(WallCoef));
+    }
     if (rc) return rc;
     c->params_dirty = false;
     return LBM_OK;
@@ -290,11 +305,10 @@ StepArgs step_args(const lbm_ctx* c, int parity) {
     a.bidx = c->bidx;
     a.bwall = c->bwall;
     a.bio = c->bio;
-    a.bk = c->bk;
+    a.bq = c->bq;
     a.bw = c->bw;
     a.ip = c->ip;
     a.iop = c->iop;
-    a.kinv = c->kinv;
     a.clock = c->clock;
     a.wf = c->wf;
     a.stretch = c->stretch;
@@ -589,6 +603,10 @@ int lbm_create_geometry(lbm_ctx** out, const lbm_instance_desc* inst, int n_inst
         rc = rc ? rc : dalloc(c, (void**)&c->bwall, ni * 4);
         rc = rc ? rc : dalloc(c, (void**)&c->bio, ni * 4);
         rc = rc ? rc : dalloc(c, (void**)&c->bk, ni * 4);
+        rc = rc ? rc : dalloc(c, (void**)&c->bq, std::max<int64_t>(1, ni) * sizeof(WallCoef));
+        c->rec_k.assign(bl.kidx.begin(), bl.kidx.end());
+        c->rec_inst.resize(bl.wall.size());
+        for (size_t j = 0; j < bl.wall.size(); ++j) c->rec_inst[j] = (int32_t)(bl.wall[j] >> 19);
         rc = rc ? rc : dalloc(c, (void**)&c->bw, ni * 4);
         rc = rc ? rc : dalloc(c, (void**)&c->wf, nwf * sizeof(WfRec));
         rc = rc ? rc : dalloc(c, (void**)&c->stretch, cm.stretch.size() * 4);
@@ -912,10 +930,14 @@ int lbm_get_info(const lbm_ctx* c, lbm_info* info) {
     info->bytes_per_site_algorithmic = 2.0 * Q * (double)c->esize;
     const double N = (double)std::max<int64_t>(1, c->plan.N);
     if (c->ibits == 0)
+        // populations; wavefront records; stretches; link mask per
+        // irregular site; wall and iolet words and wall coefficients per
+        // site with boundary-rule links; full offsets of exceptional sites
         info->bytes_per_site_model = 2.0 * Q * (double)c->esize + 48.0 / 64.0 +
                                      32.0 * (double)c->n_stretch / N +
-                                     (double)c->n_irr / N * (4.0 + 20.0) +
-                                     (double)c->n_exc / N * 72.0;
+                                     4.0 * (double)c->n_irr / N +
+                                     (8.0 + sizeof(WallCoef)) * (double)c->nb / N +
+                                     72.0 * (double)c->n_exc / N;
     else
         info->bytes_per_site_model = 2.0 * Q * (double)c->esize + 18.0 * (c->ibits / 8) +
                                      (double)c->nb / N * 24.0;
