@@ -37,20 +37,25 @@ def make_oracle(p: Problem) -> oracle.Oracle:
     return o
 
 
-def configure(lat: lbm.Lattice, inst: int, p: Problem):
+def configure(lat: lbm.Lattice, inst: int, p: Problem, init=True):
     lat.set_wall(inst, p.mode, F=p.F, P0=p.P0, k=p.k)
     for i, q in p.iolets.items():
         lat.set_iolet(inst, i, q["kind"], q["a0"], q.get("amp", 0.0), q.get("period", 1.0),
                       q.get("phase", 0.0), q.get("direction"))
-    lat.init_fields(inst, p.rho0, p.u0)
+    if init:
+        lat.init_fields(inst, p.rho0, p.u0)
 
 
 def make_lattice(problems: List[Problem], dtype: str) -> lbm.Lattice:
     taus = {p.tau for p in problems}
     assert len(taus) == 1
     lat = lbm.Lattice([p.geo for p in problems], dtype=dtype, tau=problems[0].tau)
+    # all wall modes first (a mode change rebuilds the tables once), then
+    # the initial states
     for k, p in enumerate(problems):
-        configure(lat, k, p)
+        configure(lat, k, p, init=False)
+    for k, p in enumerate(problems):
+        lat.init_fields(k, p.rho0, p.u0)
     return lat
 
 

@@ -288,3 +288,62 @@ def test_batch_of_tubes_and_bifurcations():
         record(f"sweep_inst{k}", e, dtype="f32", steps=500)
         assert e["u"] <= 1e-5 and e["p"] <= 1e-5
     lat.close()
+
+
+def _from_workload(wl, k, rng):
+    """Problem of instance k of a named workload, from a perturbed state
+    (density 1 +- 1e-3, velocity +- 2e-3 per component)."""
+    p, g = wl.params[k], wl.geoms[k]
+    n = g.n_fluid
+    return H.Problem(geo=g, tau=wl.tau, mode=p.mode, F=p.F, P0=p.P0, k=list(p.k),
+                     iolets=dict(p.iolets), rho0=1 + 1e-3 * rng.uniform(-1, 1, n),
+                     u0=2e-3 * rng.uniform(-1, 1, (n, 3)))
+
+
+def test_full_size_tree_parity():
+    """The 7,484,227-site Murray tree of the benchmark (79 stiffness
+    segments, 48 outlets), in the benchmark's launch configuration
+    (autotuned), 100 steps against the oracle over every site: FP32 within
+    1e-5 on u and p; FP16 storage stated (bounded loosely)."""
+    from paper_2108_08783_amd import workloads
+    wl = workloads.tree()
+    p = _from_workload(wl, 0, np.random.default_rng(31))
+    steps = 100
+    o = H.make_oracle(p)
+    o.step(steps)
+    ref = o.read()
+    del o
+    for dtype, bound in (("f32", 1e-5), ("f16", 5e-3)):
+        lat = H.make_lattice([p], dtype)
+        lat.autotune(16)
+        lat.step(steps)
+        e = H.errors(lat.read_fields(0), ref, P0=p.P0)
+        record("tree_full_size", e, dtype=dtype, steps=steps, launch=lat.info())
+        assert e["u"] <= bound and e["p"] <= bound, dtype
+        lat.close()
+
+
+def test_full_size_sweep_parity_sampled():
+    """The 64-instance sweep of the benchmark (19.7M sites, one batched
+    launch per step, autotuned), 100 steps; six instances drawn with a fixed
+    seed are compared with the oracle over every one of their sites."""
+    from paper_2108_08783_amd import workloads
+    wl = workloads.sweep()
+    rng = np.random.default_rng(47)
+    probs = [_from_workload(wl, k, rng) for k in range(len(wl.geoms))]
+    pick = sorted(rng.choice(len(probs), 6, replace=False).tolist())
+    steps = 100
+    refs = {}
+    for k in pick:
+        o = H.make_oracle(probs[k])
+        o.step(steps)
+        refs[k] = o.read()
+    for dtype, bound in (("f32", 1e-5), ("f16", 5e-3)):
+        lat = H.make_lattice(probs, dtype)
+        lat.autotune(16)
+        lat.step(steps)
+        for k in pick:
+            e = H.errors(lat.read_fields(k), refs[k], P0=probs[k].P0)
+            record(f"sweep64_inst{k}", e, dtype=dtype, steps=steps)
+            assert e["u"] <= bound and e["p"] <= bound, (dtype, k)
+        lat.close()
