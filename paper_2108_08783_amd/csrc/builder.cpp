@@ -5,10 +5,40 @@
 #include <cmath>
 #include <cstring>
 #include <sstream>
+#include <thread>
 
 #include "d3q19.hpp"
 
 namespace lbm {
+
+namespace {
+
+// Host worker threads for the O(N) passes (at most 16: the CPU share of one
+// GPU on a shared host).
+int n_workers(int64_t work) {
+    const unsigned h = std::thread::hardware_concurrency();
+    const int t = (int)std::min<unsigned>(h ? h : 1u, 16u);
+    return work < (int64_t)1 << 16 ? 1 : t;
+}
+
+// Runs f(t, begin, end) on contiguous chunks [begin, end) of [0, n), one per
+// worker, in order of t.
+template <typename F>
+void parallel_chunks(int64_t n, int workers, F f) {
+    if (workers <= 1) {
+        f(0, (int64_t)0, n);
+        return;
+    }
+    std::vector<std::thread> th;
+    const int64_t chunk = (n + workers - 1) / workers;
+    for (int t = 0; t < workers; ++t) {
+        const int64_t b = std::min(n, t * chunk), e = std::min(n, (t + 1) * chunk);
+        th.emplace_back([=, &f] { f(t, b, e); });
+    }
+    for (auto& x : th) x.join();
+}
+
+}  // namespace
 
 std::string build_plan(const lbm_instance_desc* desc, int n_inst, Plan& plan) {
     if (n_inst <= 0) return "n_inst must be positive";
@@ -16,7 +46,8 @@ std::string build_plan(const lbm_instance_desc* desc, int n_inst, Plan& plan) {
     plan = Plan();
     plan.inst.resize(n_inst);
     int64_t total = 0;
-    // pass 1: counts and validation
+    // pass 1: fluid voxels per z-slice (parallel over slices), validation
+    std::vector<std::vector<int64_t>> slice_start(n_inst);
     for (int k = 0; k < n_inst; ++k) {
         const lbm_instance_desc& d = desc[k];
         if (!d.labels) return "instance " + std::to_string(k) + ": labels is NULL";
@@ -25,23 +56,33 @@ std::string build_plan(const lbm_instance_desc* desc, int n_inst, Plan& plan) {
         InstanceGeom& g = plan.inst[k];
         g.nx = d.nx; g.ny = d.ny; g.nz = d.nz;
         g.offset = total;
-        int64_t n = 0;
         const int64_t nxy = (int64_t)d.nx * d.ny;
-        for (int z = 0; z < d.nz; ++z)
-            for (int y = 0; y < d.ny; ++y) {
-                const uint8_t* row = d.labels + z * nxy + (int64_t)y * d.nx;
-                const bool edge = (z == 0 || z == d.nz - 1 || y == 0 || y == d.ny - 1);
-                for (int x = 0; x < d.nx; ++x) {
-                    if (row[x] != LBM_LABEL_FLUID) continue;
-                    if (edge || x == 0 || x == d.nx - 1) {
-                        std::ostringstream s;
-                        s << "instance " << k << ": fluid voxel on the array border at (" << x
-                          << "," << y << "," << z << ")";
-                        return s.str();
+        std::vector<int64_t> cnt(d.nz, 0);
+        std::vector<std::string> err(16);
+        const int W = n_workers(nxy * d.nz);
+        parallel_chunks(d.nz, W, [&](int t, int64_t z0, int64_t z1) {
+            for (int64_t z = z0; z < z1 && err[t].empty(); ++z)
+                for (int y = 0; y < d.ny; ++y) {
+                    const uint8_t* row = d.labels + z * nxy + (int64_t)y * d.nx;
+                    const bool edge = (z == 0 || z == d.nz - 1 || y == 0 || y == d.ny - 1);
+                    for (int x = 0; x < d.nx; ++x) {
+                        if (row[x] != LBM_LABEL_FLUID) continue;
+                        if (edge || x == 0 || x == d.nx - 1) {
+                            std::ostringstream m;
+                            m << "instance " << k << ": fluid voxel on the array border at (" << x
+                              << "," << y << "," << z << ")";
+                            err[t] = m.str();
+                            break;
+                        }
+                        ++cnt[z];
                     }
-                    ++n;
                 }
-            }
+        });
+        for (const auto& e : err)
+            if (!e.empty()) return e;
+        slice_start[k].assign(d.nz + 1, 0);
+        for (int z = 0; z < d.nz; ++z) slice_start[k][z + 1] = slice_start[k][z] + cnt[z];
+        const int64_t n = slice_start[k][d.nz];
         if (n == 0) return "instance " + std::to_string(k) + ": no fluid voxel";
         g.n = n;
         total += n;
@@ -54,79 +95,112 @@ std::string build_plan(const lbm_instance_desc* desc, int n_inst, Plan& plan) {
     plan.site_seg.assign(N, 0);
     plan.site_w.assign(N, 1.0f);
     plan.site_inst.assign(N, 0);
-    // pass 2: index grid and link classification per instance
+    // pass 2 per instance: index grid, then the link classification of every
+    // site; z-slabs in parallel, per-slab results merged in slab order
+    struct Part {
+        std::string err;
+        int64_t max_abs = 0, n_wall = 0, n_io = 0;
+        int max_seg = 0, max_io = -1;
+        std::vector<uint8_t> used;
+        std::vector<int32_t> wall_site;
+        std::vector<double> wall_normal;
+    };
     for (int k = 0; k < n_inst; ++k) {
         const lbm_instance_desc& d = desc[k];
         InstanceGeom& g = plan.inst[k];
         const int64_t nxy = (int64_t)d.nx * d.ny, nvox = nxy * d.nz;
+        const std::vector<int64_t>& ss = slice_start[k];
         std::vector<int32_t> index(nvox, -1);
-        int32_t next = 0;
-        for (int64_t v = 0; v < nvox; ++v)
-            if (d.labels[v] == LBM_LABEL_FLUID) index[v] = next++;
+        const int W = n_workers(nvox);
+        parallel_chunks(d.nz, W, [&](int, int64_t z0, int64_t z1) {
+            for (int64_t z = z0; z < z1; ++z) {
+                int32_t next = (int32_t)ss[z];
+                for (int64_t v = z * nxy; v < (z + 1) * nxy; ++v)
+                    if (d.labels[v] == LBM_LABEL_FLUID) index[v] = next++;
+            }
+        });
+        std::vector<Part> parts(W);
+        parallel_chunks(d.nz - 2, W, [&](int t, int64_t b, int64_t e) {
+            Part& P = parts[t];
+            P.used.assign(254, 0);
+            for (int64_t z = b + 1; z < e + 1 && P.err.empty(); ++z) {
+                int64_t s = ss[z];
+                for (int y = 1; y < d.ny - 1 && P.err.empty(); ++y)
+                    for (int x = 1; x < d.nx - 1; ++x) {
+                        const int64_t v = z * nxy + (int64_t)y * d.nx + x;
+                        if (d.labels[v] != LBM_LABEL_FLUID) continue;
+                        const int64_t gs = g.offset + s;
+                        plan.site_inst[gs] = (uint32_t)k;
+                        const uint16_t seg = d.segment ? d.segment[v] : 0;
+                        plan.site_seg[gs] = seg;
+                        if (seg > P.max_seg) P.max_seg = seg;
+                        plan.site_w[gs] = d.iolet_weight ? d.iolet_weight[v] : 1.0f;
+                        int nwall = 0, sid = -1;
+                        float gx = 0, gy = 0, gz = 0;
+                        for (int i = 1; i < Q; ++i) {
+                            const int64_t u = v - CX[i] - (int64_t)CY[i] * d.nx - CZ[i] * nxy;
+                            const uint8_t lab = d.labels[u];
+                            int32_t code;
+                            if (lab == LBM_LABEL_FLUID) {
+                                const int64_t off = (int64_t)index[u] - s;
+                                code = (int32_t)off;
+                                const int64_t a = off < 0 ? -off : off;
+                                if (a > P.max_abs) P.max_abs = a;
+                            } else if (lab == LBM_LABEL_WALL) {
+                                code = H_WALL;
+                                ++nwall;
+                                gx -= CX[i]; gy -= CY[i]; gz -= CZ[i];
+                                ++P.n_wall;
+                            } else {
+                                const int id = lab - LBM_LABEL_IOLET0;
+                                if (sid >= 0 && sid != id) {
+                                    std::ostringstream m;
+                                    m << "instance " << k << ": fluid site (" << x << "," << y << ","
+                                      << z << ") touches iolets " << sid << " and " << id;
+                                    P.err = m.str();
+                                }
+                                sid = id;
+                                P.used[id] = 1;
+                                if (id > P.max_io) P.max_io = id;
+                                code = H_IOLET;
+                                ++P.n_io;
+                            }
+                            plan.nbr[(size_t)(i - 1) * N + gs] = code;
+                        }
+                        if (sid >= 0) plan.site_iolet[gs] = (uint8_t)sid;
+                        if (nwall > 0) {
+                            P.wall_site.push_back((int32_t)gs);
+                            double nxv, nyv, nzv;
+                            if (d.normal) {
+                                nxv = d.normal[3 * v]; nyv = d.normal[3 * v + 1]; nzv = d.normal[3 * v + 2];
+                            } else {
+                                nxv = gx; nyv = gy; nzv = gz;
+                            }
+                            const double nn = std::sqrt(nxv * nxv + nyv * nyv + nzv * nzv);
+                            if (nn > 0) { nxv /= nn; nyv /= nn; nzv /= nn; }
+                            P.wall_normal.push_back(nxv);
+                            P.wall_normal.push_back(nyv);
+                            P.wall_normal.push_back(nzv);
+                        }
+                        ++s;
+                    }
+            }
+        });
         g.iolet_used.assign(254, 0);
         int max_seg = 0, max_io = -1;
         g.wall_begin = (int64_t)plan.wall_site.size();
-        int64_t s = 0;
-        for (int z = 1; z < d.nz - 1; ++z)
-            for (int y = 1; y < d.ny - 1; ++y)
-                for (int x = 1; x < d.nx - 1; ++x) {
-                    const int64_t v = z * nxy + (int64_t)y * d.nx + x;
-                    if (d.labels[v] != LBM_LABEL_FLUID) continue;
-                    const int64_t gs = g.offset + s;
-                    plan.site_inst[gs] = (uint32_t)k;
-                    const uint16_t seg = d.segment ? d.segment[v] : 0;
-                    plan.site_seg[gs] = seg;
-                    if (seg > max_seg) max_seg = seg;
-                    plan.site_w[gs] = d.iolet_weight ? d.iolet_weight[v] : 1.0f;
-                    int nwall = 0, sid = -1;
-                    float gx = 0, gy = 0, gz = 0;
-                    for (int i = 1; i < Q; ++i) {
-                        const int64_t u = v - CX[i] - (int64_t)CY[i] * d.nx - CZ[i] * nxy;
-                        const uint8_t lab = d.labels[u];
-                        int32_t code;
-                        if (lab == LBM_LABEL_FLUID) {
-                            const int64_t off = (int64_t)index[u] - s;
-                            code = (int32_t)off;
-                            const int64_t a = off < 0 ? -off : off;
-                            if (a > plan.max_abs_offset) plan.max_abs_offset = a;
-                        } else if (lab == LBM_LABEL_WALL) {
-                            code = H_WALL;
-                            ++nwall;
-                            gx -= CX[i]; gy -= CY[i]; gz -= CZ[i];
-                            ++plan.n_wall_links;
-                        } else {
-                            const int id = lab - LBM_LABEL_IOLET0;
-                            if (sid >= 0 && sid != id) {
-                                std::ostringstream m;
-                                m << "instance " << k << ": fluid site (" << x << "," << y << ","
-                                  << z << ") touches iolets " << sid << " and " << id;
-                                return m.str();
-                            }
-                            sid = id;
-                            g.iolet_used[id] = 1;
-                            if (id > max_io) max_io = id;
-                            code = H_IOLET;
-                            ++plan.n_iolet_links;
-                        }
-                        plan.nbr[(size_t)(i - 1) * N + gs] = code;
-                    }
-                    if (sid >= 0) plan.site_iolet[gs] = (uint8_t)sid;
-                    if (nwall > 0) {
-                        plan.wall_site.push_back((int32_t)gs);
-                        double nxv, nyv, nzv;
-                        if (d.normal) {
-                            nxv = d.normal[3 * v]; nyv = d.normal[3 * v + 1]; nzv = d.normal[3 * v + 2];
-                        } else {
-                            nxv = gx; nyv = gy; nzv = gz;
-                        }
-                        const double nn = std::sqrt(nxv * nxv + nyv * nyv + nzv * nzv);
-                        if (nn > 0) { nxv /= nn; nyv /= nn; nzv /= nn; }
-                        plan.wall_normal.push_back(nxv);
-                        plan.wall_normal.push_back(nyv);
-                        plan.wall_normal.push_back(nzv);
-                    }
-                    ++s;
-                }
+        for (const Part& P : parts) {
+            if (!P.err.empty()) return P.err;
+            plan.max_abs_offset = std::max(plan.max_abs_offset, P.max_abs);
+            plan.n_wall_links += P.n_wall;
+            plan.n_iolet_links += P.n_io;
+            max_seg = std::max(max_seg, P.max_seg);
+            max_io = std::max(max_io, P.max_io);
+            for (size_t j = 0; j < P.used.size(); ++j) g.iolet_used[j] |= P.used[j];
+            plan.wall_site.insert(plan.wall_site.end(), P.wall_site.begin(), P.wall_site.end());
+            plan.wall_normal.insert(plan.wall_normal.end(), P.wall_normal.begin(),
+                                    P.wall_normal.end());
+        }
         g.wall_end = (int64_t)plan.wall_site.size();
         g.n_seg = max_seg + 1;
         g.n_iolet = max_io + 1;
@@ -140,9 +214,10 @@ void build_boundary(const Plan& plan, const std::vector<int>& mode,
     out = BoundaryList();
     const int64_t N = plan.N;
     out.rec_of_site.assign(N, -1);
-    for (int64_t x = 0; x < N; ++x) {
+    auto classify = [&](int64_t x, uint32_t& wmask, uint32_t& imask) {
         const uint32_t k = plan.site_inst[x];
-        uint32_t wmask = 0, imask = 0;
+        wmask = 0;
+        imask = 0;
         bool irregular = false;
         for (int i = 1; i < Q; ++i) {
             const int32_t c = plan.nbr[(size_t)(i - 1) * N + x];
@@ -150,17 +225,47 @@ void build_boundary(const Plan& plan, const std::vector<int>& mode,
             if (c == H_WALL && mode[k] == LBM_WALL_ELASTIC) wmask |= 1u << i;
             if (c == H_IOLET) imask |= 1u << i;
         }
-        if (!irregular) continue;
-        const int32_t id = (int32_t)out.site.size();
-        out.rec_of_site[x] = id;
-        out.site.push_back((int32_t)x);
-        out.wall.push_back(wmask | (k << 19));
-        const uint32_t slot = imask ? (uint32_t)(iolet_off[k] + plan.site_iolet[x]) : 0u;
-        out.io.push_back(imask | (slot << 19));
-        out.kidx.push_back(seg_off[k] + plan.site_seg[x]);
-        out.weight.push_back(plan.site_w[x]);
-        if (wmask | imask) out.ghost.push_back(id);
+        return irregular;
+    };
+    // irregular sites per chunk, then every record at its final position
+    const int W = n_workers(N);
+    std::vector<int64_t> cnt(W + 1, 0), gcnt(W + 1, 0);
+    parallel_chunks(N, W, [&](int t, int64_t b, int64_t e) {
+        uint32_t wm, im;
+        for (int64_t x = b; x < e; ++x)
+            if (classify(x, wm, im)) {
+                ++cnt[t + 1];
+                if (wm | im) ++gcnt[t + 1];
+            }
+    });
+    for (int t = 0; t < W; ++t) {
+        cnt[t + 1] += cnt[t];
+        gcnt[t + 1] += gcnt[t];
     }
+    const int64_t nr = cnt[W];
+    out.site.resize(nr);
+    out.wall.resize(nr);
+    out.io.resize(nr);
+    out.kidx.resize(nr);
+    out.weight.resize(nr);
+    out.ghost.resize(gcnt[W]);
+    parallel_chunks(N, W, [&](int t, int64_t b, int64_t e) {
+        int64_t id = cnt[t], gid = gcnt[t];
+        uint32_t wmask, imask;
+        for (int64_t x = b; x < e; ++x) {
+            if (!classify(x, wmask, imask)) continue;
+            const uint32_t k = plan.site_inst[x];
+            out.rec_of_site[x] = (int32_t)id;
+            out.site[id] = (int32_t)x;
+            out.wall[id] = wmask | (k << 19);
+            const uint32_t slot = imask ? (uint32_t)(iolet_off[k] + plan.site_iolet[x]) : 0u;
+            out.io[id] = imask | (slot << 19);
+            out.kidx[id] = seg_off[k] + plan.site_seg[x];
+            out.weight[id] = plan.site_w[x];
+            if (wmask | imask) out.ghost[gid++] = (int32_t)id;
+            ++id;
+        }
+    });
 }
 
 namespace {
@@ -285,8 +390,8 @@ std::string build_compressed(const Plan& plan, const BoundaryList& bl,
     if (out.stretch.empty()) out.stretch.assign(8, 0);
     if (nirr != out.n_irr) return "compressed addressing: irregular-site count mismatch";
 
-    // check: the device's reconstruction reproduces the table at every site
-    for (int64_t x = 0; x < N; ++x) {
+    auto check_range = [&](int64_t b0, int64_t e0) -> std::string {
+    for (int64_t x = b0; x < e0; ++x) {
         const WfRec& R = out.wf[x >> 6];
         const int l = (int)(x & 63);
         const uint64_t bit = 1ull << l, below = bit - 1ull;
@@ -321,8 +426,19 @@ std::string build_compressed(const Plan& plan, const BoundaryList& bl,
         if (ghost_tab != ghost_rec)
             return "compressed addressing: boundary-link flag mismatch at site " + std::to_string(x);
     }
+        return std::string();
+    };
+    // check: the device's reconstruction reproduces the table at every site
+    const int W = n_workers(N);
+    std::vector<std::string> errs(W);
+    parallel_chunks(N, W, [&](int t, int64_t b, int64_t e) {
+        errs[t] = check_range(b, e);
+    });
+    for (const auto& e : errs)
+        if (!e.empty()) return e;
     return "";
 }
+
 
 void refresh_compressed(const BoundaryList& bl, const std::vector<int32_t>& nbr_dev32,
                         int64_t n_pad, Compressed& c) {
@@ -351,7 +467,8 @@ void build_device_nbr(const Plan& plan, const std::vector<int>& mode, int64_t n_
                       std::vector<I>& out) {
     const int64_t N = plan.N;
     out.assign((size_t)18 * n_pad, (I)0);
-    for (int i = 1; i < Q; ++i) {
+    parallel_chunks(18, std::min(18, n_workers(18 * N)), [&](int, int64_t i0, int64_t i1) {
+    for (int i = (int)i0 + 1; i < (int)i1 + 1; ++i) {
         const int32_t* src = plan.nbr.data() + (size_t)(i - 1) * N;
         I* dst = out.data() + (size_t)(i - 1) * n_pad;
         for (int64_t x = 0; x < N; ++x) {
@@ -367,6 +484,7 @@ void build_device_nbr(const Plan& plan, const std::vector<int>& mode, int64_t n_
         // padding sites read their own rest slot (never stored back)
         for (int64_t x = N; x < n_pad; ++x) dst[x] = Sentinel<I>::BB;
     }
+    });
 }
 
 template void build_device_nbr<int32_t>(const Plan&, const std::vector<int>&, int64_t,
