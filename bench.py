@@ -133,6 +133,29 @@ def summary(r, dtype, with_traffic=False):
     return out
 
 
+def cpu_one_thread(target_s=6.0):
+    """The oracle on the same tube with one OpenMP thread, in a child process
+    (the thread count is fixed when the oracle library loads)."""
+    import subprocess
+    code = (
+        "import json, sys, time; sys.path.insert(0, %r)\n"
+        "import bench, oracle\n"
+        "from paper_2108_08783_amd import workloads\n"
+        "wl = workloads.tube32(); g = wl.geoms[0]\n"
+        "o = oracle.Oracle(g.labels, wl.tau, segment=g.segment, normal=g.normal, iolet_weight=g.iolet_weight)\n"
+        "bench.oracle_configure(o, wl); o.step(1)\n"
+        "t0 = time.perf_counter(); o.step(1); dt = time.perf_counter() - t0\n"
+        "n = max(2, int(%f / max(dt, 1e-6)))\n"
+        "t0 = time.perf_counter(); o.step(n); el = time.perf_counter() - t0\n"
+        "print(json.dumps(dict(value=o.n * n / el / 1e6, unit='MLUPS', cores=oracle.num_threads(), "
+        "sample='%%d steps of the 1640960-site elastic tube (FP64), %%.1f s' %% (n, el))))\n"
+    ) % (ROOT, target_s)
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                       check=True)
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
 def cpu_baseline(wl, target_s=15.0):
     """The FP64 oracle on the same tube, timed on this host's cores."""
     import oracle
@@ -215,11 +238,25 @@ def main():
             secondary["sweep64_" + dt] = summary(r, dt)
             print(f"[bench] sweep {dt}: {r['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
         del sw
+        # the paper's R = 100 dx verification cylinder (41.9M sites, 6.4 GB
+        # of FP32 populations): 1000 iterations beside its Table 1 entry
+        from paper_2108_08783_amd import verification
+        row = verification.timing([100], "f32")[0]
+        secondary["paper_cylinder_R100_f32"] = dict(
+            sites=row["sites"], elastic_s_per_1000=round(row["elastic_s"], 4),
+            rigid_s_per_1000=round(row["rigid_s"], 4), elastic_glups=round(row["elastic_glups"], 2),
+            roofline_frac=round(2 * 19 * 4 * row["elastic_glups"] * 1e9 / (PEAK_GBS * 1e9), 4),
+            paper_elastic_s_per_1000=row["paper_elastic_s"], paper_cores=6000)
+        print(f"[bench] paper cylinder R=100: {row['elastic_s']:.3f} s per 1000 iterations",
+              file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(tube)
         print(f"[bench] oracle: {cpu['value']:.1f} MLUPS on {cpu['cores']} threads",
+              file=sys.stderr, flush=True)
+        secondary["oracle_1_thread"] = cpu_one_thread()
+        print(f"[bench] oracle, 1 thread: {secondary['oracle_1_thread']['value']:.2f} MLUPS",
               file=sys.stderr, flush=True)
 
     info = main_run["info"]
