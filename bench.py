@@ -191,7 +191,7 @@ def main():
                     help="only run the plain-copy bandwidth probe")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); "
+        print(f"bench.py: the library runs on one GPU only (got --gpus {args.gpus}); "
               "instances and domains would shard across GPUs as described in DESIGN.md",
               file=sys.stderr)
         sys.exit(2)

@@ -241,7 +241,7 @@ int lbm_instance_sites(const lbm_ctx* ctx, int inst, int64_t* n);
  * the same blocks as all other sites, which apply the link rules in place;
  * 0: they are skipped there and updated by a compacted list of boundary
  * sites in blocks appended to the same launch.  Both modes compute the same
- * link rule.  sites_per_lane: 1 (the only value this build accepts; two
+ * link rule.  sites_per_lane: 1 (the only value accepted; two
  * sites per lane measured slower on gfx950).  A value of -1 keeps the
  * current setting.  No setting changes the arithmetic. */
 int lbm_set_launch(lbm_ctx* ctx, int block_size, int index_bits, int use_graph, int xcd_remap,

@@ -76,8 +76,7 @@ def load():
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
-        raise RuntimeError(f"{LIB_PATH} is not built: run paper_2108_08783_amd/build.py "
-                           "(or __graft_entry__.build()) first")
+        raise RuntimeError(f"{LIB_PATH} is not built: run paper_2108_08783_amd/build.py first")
     # torch ships its own HIP runtime; load it first so that the library and
     # torch share one runtime in the process (the library's dependency is
     # then resolved to the already-loaded copy).

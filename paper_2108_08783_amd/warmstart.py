@@ -4,7 +4,7 @@ A per-site network predicts density and velocity of the periodic
 (cycle-to-cycle converged) flow from local geometry and drive features; the
 prediction initialises the populations at equilibrium (Sec. 2.1 eq. feq),
 after which the ordinary update runs unchanged.  The zero-velocity start is
-the fallback and the judge: both starts must converge to the same periodic
+the fallback and the reference: both starts must converge to the same periodic
 state, and the figure of merit is the number of cardiac cycles needed.
 
 Features (16 per site, host-side, from the generator's segment list):
