@@ -107,7 +107,10 @@ def random_box_problem(seed, mode=lbm.ELASTIC, shape=(9, 10, 11)):
     io = {0: dict(kind=lbm.DENSITY, a0=1.002, amp=0.3, period=17.0, phase=0.4),
           1: dict(kind=lbm.VELOCITY, a0=0.03, amp=0.5, period=11.0, phase=-1.0,
                   direction=g.iolets[1]["direction"])}
-    present = {int(v) - 2 for v in np.unique(g.labels) if v >= 2}
+    # only iolets that some fluid site links to (a label with no fluid
+    # neighbour is rejected by the library as a mis-set iolet)
+    hi = g.labels.shape[::-1]
+    present = {i for i in (0, 1) if inputs._touches_fluid(g.labels, 2 + i, (0, 0, 0), hi)}
     io = {k: v for k, v in io.items() if k in present}
     n = g.n_fluid
     u0 = 0.02 * rng.uniform(-1, 1, (n, 3))

@@ -98,6 +98,47 @@ def test_random_boxes_every_link_type(dtype, seed, fused, addr):
     assert e["u"] <= 10 * tol and e["p"] <= tol and e["wss"] <= 100 * tol
 
 
+@pytest.mark.parametrize("dtype", ["f16", "bf16"])
+@pytest.mark.parametrize("fused", [1, 0])
+def test_random_boxes_16bit_storage(dtype, fused):
+    """The random boxes (about a third of their sites have links in several
+    runs per row, so they take the per-site offset path) with 16-bit
+    deviation storage, where the boundary records are read at use time
+    rather than ahead of the gathers."""
+    p = H.random_box_problem(2)
+    g, r = run_pair(p, dtype, 60, launch=dict(boundary_fused=fused))
+    e = H.errors(g, r, P0=p.P0)
+    record("random_box_2", e, dtype=dtype, steps=60, fused=fused)
+    bound = {"f16": 1e-2, "bf16": 5e-2}[dtype]
+    assert e["u"] <= bound and e["p"] <= bound
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_many_random_boxes_in_one_context(dtype):
+    """Twelve random boxes of different shapes, alternating bounce-back and
+    elastic walls with their own stiffness segments, packed into one
+    context: wavefronts that straddle instances, per-instance records and
+    parameters; each instance against its own oracle run."""
+    rng = np.random.default_rng(77)
+    probs = []
+    for i in range(12):
+        shape = tuple(int(v) for v in rng.integers(5, 13, 3))
+        mode = lbm.BOUNCEBACK if i % 2 else lbm.ELASTIC
+        p = H.random_box_problem(100 + i, mode=mode, shape=shape)
+        p.F = float(rng.uniform(0.2, 0.9))
+        p.k = [float(v) for v in inputs.log_uniform(rng, 1e-3, 1e-1, size=3)]
+        probs.append(p)
+    lat = H.make_lattice(probs, dtype)
+    lat.step(80)
+    for k, p in enumerate(probs):
+        o = H.make_oracle(p)
+        o.step(80)
+        e = H.errors(lat.read_fields(k), o.read(), P0=p.P0)
+        record(f"many_boxes_inst{k}", e, dtype=dtype, steps=80, mode=p.mode)
+        assert e["u"] <= 10 * TOL[dtype] and e["p"] <= TOL[dtype]
+    lat.close()
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_batch_of_uneven_instances(dtype):
     """Several instances of different size and wall mode in one context,
