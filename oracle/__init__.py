@@ -52,6 +52,7 @@ def _load():
     lib.orc_velocity_set.argtypes = [P, P]
     lib.orc_feq.argtypes = [ctypes.c_double] * 4 + [P]
     lib.orc_set_wall.argtypes = [P, ctypes.c_int, ctypes.c_double, ctypes.c_double, P, ctypes.c_int]
+    lib.orc_set_wall_F.argtypes = [P, P, ctypes.c_int]
     lib.orc_set_iolet.argtypes = [P, ctypes.c_int, ctypes.c_int] + [ctypes.c_double] * 4 + [P]
     lib.orc_init_fields.argtypes = [P, P, P]
     lib.orc_set_populations.argtypes = [P, P]
@@ -128,6 +129,13 @@ class Oracle:
     def set_wall(self, mode, F=0.0, P0=1.0 / 3.0, k=(1.0,)):
         k = np.ascontiguousarray(k, dtype=np.float64)
         _load().orc_set_wall(self._h, int(mode), float(F), float(P0), _ptr(k), len(k))
+
+    def set_wall_F(self, F):
+        """Slip ratio per wall segment, replacing the single F of set_wall
+        (one value per segment given to set_wall)."""
+        F = np.ascontiguousarray(F, dtype=np.float64)
+        if _load().orc_set_wall_F(self._h, _ptr(F), len(F)) != 0:
+            raise ValueError("one F per wall segment is required")
 
     def set_iolet(self, iolet_id, kind, a0, amp=0.0, period=1.0, phase=0.0, direction=(0, 0, 0)):
         d = np.ascontiguousarray(direction, dtype=np.float64)

@@ -47,6 +47,21 @@ def slip_half_width_sq(Yw, F):
     return (Yw * Yw - F * (Yw - 1.0) ** 2) / (1.0 - F)
 
 
+def slip_poiseuille_two_walls(y, Yw, F_lo, F_hi, A):
+    """Steady plane Poiseuille u(y) = -A y^2 + beta y + gamma between wall
+    nodes at y = -Y_w and y = +Y_w whose slip ratios differ (the elastic
+    rule of Sec. 2.3 with Delta E = 0 on each wall: u(wall node) = F u(last
+    fluid node)).  The two slip conditions are linear in (beta, gamma)."""
+    y1 = Yw - 1.0
+    # lower wall: u(-Yw) - F_lo u(-y1) = 0; upper wall: u(Yw) - F_hi u(y1) = 0
+    M = np.array([[-Yw + F_lo * y1, 1.0 - F_lo],
+                  [Yw - F_hi * y1, 1.0 - F_hi]])
+    rhs = np.array([A * (Yw * Yw - F_lo * y1 * y1), A * (Yw * Yw - F_hi * y1 * y1)])
+    beta, gamma = np.linalg.solve(M, rhs)
+    y = np.asarray(y, float)
+    return -A * y * y + beta * y + gamma
+
+
 def duct_poiseuille(x, y, a, b, G, mu, nterms=101):
     """Fully developed flow in the rectangle |x| < a, |y| < b (Fourier series,
     e.g. White, Viscous Fluid Flow, Sec. 3-3)."""

@@ -83,6 +83,7 @@ typedef struct {
     int mode;              /* 0 bounce-back, 1 elastic */
     double F, P0;
     double *k_seg;
+    double *F_seg;         /* slip ratio per segment, F by default */
     int n_seg;
     int io_kind[MAX_IOLETS];
     double io_a0[MAX_IOLETS], io_amp[MAX_IOLETS], io_period[MAX_IOLETS], io_phase[MAX_IOLETS];
@@ -132,7 +133,7 @@ void orc_destroy(void *h) {
     orc_t *o = (orc_t *)h;
     if (!o) return;
     free(o->index); free(o->site_x); free(o->site_y); free(o->site_z); free(o->labels);
-    free(o->seg); free(o->normal); free(o->iolet_w); free(o->k_seg);
+    free(o->seg); free(o->normal); free(o->iolet_w); free(o->k_seg); free(o->F_seg);
     free(o->f); free(o->fnew); free(o->fstar);
     free(o->rho); free(o->ux); free(o->uy); free(o->uz);
     free(o);
@@ -196,6 +197,8 @@ void *orc_create(int nx, int ny, int nz, const uint8_t *labels, const uint16_t *
     o->n_seg = 1;
     o->k_seg = (double *)malloc(sizeof(double));
     o->k_seg[0] = 1.0;
+    o->F_seg = (double *)malloc(sizeof(double));
+    o->F_seg[0] = 0.0;
     for (int i = 0; i < n; ++i)
         for (int q = 0; q < Q; ++q) o->f[(size_t)i * Q + q] = weight(q);
     return o;
@@ -229,9 +232,26 @@ void orc_set_wall(void *h, int mode, double F, double P0, const double *k, int n
     o->F = F;
     o->P0 = P0;
     free(o->k_seg);
+    free(o->F_seg);
     o->n_seg = n_seg;
     o->k_seg = (double *)malloc(sizeof(double) * (n_seg > 0 ? n_seg : 1));
-    for (int s = 0; s < n_seg; ++s) o->k_seg[s] = k[s];
+    o->F_seg = (double *)malloc(sizeof(double) * (n_seg > 0 ? n_seg : 1));
+    for (int s = 0; s < n_seg; ++s) {
+        o->k_seg[s] = k[s];
+        o->F_seg[s] = F;
+    }
+}
+
+/* Slip ratio F per wall segment (the closing discussion of Sec. 5: F may be
+ * set locally, e.g. per vessel of a tree from the Sec. 2.3 relation between
+ * F, the Womersley number and Delta r / R).  Replaces the single F of
+ * orc_set_wall for segments 0 .. n_seg-1; returns -1 if n_seg differs from
+ * the count given to orc_set_wall. */
+int orc_set_wall_F(void *h, const double *F, int n_seg) {
+    orc_t *o = (orc_t *)h;
+    if (n_seg != o->n_seg) return -1;
+    for (int s = 0; s < n_seg; ++s) o->F_seg[s] = F[s];
+    return 0;
 }
 
 void orc_set_iolet(void *h, int id, int kind, double a0, double amp, double period, double phase,
@@ -326,7 +346,7 @@ static void step_once(orc_t *o) {
                      * linear profile between the fluid node and the extended
                      * wall at distance Delta r. */
                     double dr = wall_dr(o, s, rho);
-                    double F = o->F;
+                    double F = o->F_seg[o->seg[s]];
                     double URx = F * ux, URy = F * uy, URz = F * uz;
                     double a = (dr - 1.0) / dr;
                     double Uwx = URx + a * (ux - URx);

@@ -276,6 +276,60 @@ def test_elastic_wall_slip_poiseuille(F):
     assert errs[0] / errs[1] > 2.5
 
 
+def _two_slip_channel(H, F_lo, F_hi, tau=0.8):
+    """Wide duct whose lower and upper halves are wall segments 0 and 1 with
+    slip ratios F_lo and F_hi, infinite stiffness, density-driven; returns
+    the centre-line profile error against the two-wall slip parabola and
+    against its mirror image (the two F swapped)."""
+    W, L = 8 * H, 4 * H
+    g = inputs.duct(W, H, L)
+    g.segment[:, H // 2 + 1:, :] = 1
+    o = oracle.Oracle(g.labels, tau, segment=g.segment)
+    o.set_wall(1, F=0.5, P0=0.0, k=[1e30, 1e30])
+    o.set_wall_F([F_lo, F_hi])
+    o.set_iolet(0, 0, 1.0001)
+    o.set_iolet(1, 0, 0.9999)
+    o.init_fields()
+    nu = (tau - 0.5) / 3
+    o.step(int(3.0 * 14 * H * H / (math.pi ** 2 * nu) / (1 - max(F_lo, F_hi))))
+    rho, u, _, _ = o.read()
+    xyz = o.coords()
+    zc = L // 2
+
+    def mean_rho(z):
+        return rho[xyz[:, 2] == z].mean()
+
+    G = -(mean_rho(zc + 1) - mean_rho(zc - 1)) / 2 / 3
+    sel = (xyz[:, 2] == zc) & (xyz[:, 0] == W // 2)
+    y = xyz[sel, 1] - (H + 1) / 2
+    A = G / (2 * rho[sel].mean() * nu)
+    Yw = (H + 1) / 2
+    ua = cf.slip_poiseuille_two_walls(y, Yw, F_lo, F_hi, A)
+    swapped = cf.slip_poiseuille_two_walls(y, Yw, F_hi, F_lo, A)
+    return (np.abs(u[sel, 2] - ua).max() / ua.max(),
+            np.abs(u[sel, 2] - swapped).max() / ua.max())
+
+
+def test_elastic_wall_slip_ratio_per_segment():
+    """P5 with a local F (closing discussion of Sec. 5): the two halves of a
+    wide duct have F = 0.1 and 0.7.  The steady mid-section approaches the
+    lopsided parabola through the two slip conditions (error shrinking
+    about 2.5x per doubling, as for one F), while its mirror image stays
+    far off, so a segment mix-up fails."""
+    e4, s4 = _two_slip_channel(4, 0.1, 0.7)
+    e8, s8 = _two_slip_channel(8, 0.1, 0.7)
+    assert e8 < 0.07 and e4 / e8 > 2.2
+    assert s4 > 0.3 and s8 > 0.3
+
+
+def test_oracle_slip_ratio_per_segment_needs_one_value_per_segment():
+    g = inputs.duct(4, 4, 4)
+    o = oracle.Oracle(g.labels, 0.8)
+    o.set_wall(1, F=0.5, P0=0.0, k=[1.0, 1.0])
+    with pytest.raises(ValueError):
+        o.set_wall_F([0.1])
+
+
 def test_elastic_extension_clamp_and_monotonicity():
     """Sec. 2.4 extension law with reading R4: below P0 the wall is rigid at
     the wall node (identical to infinite stiffness); above P0 a softer wall
