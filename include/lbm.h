@@ -153,6 +153,15 @@ const char* lbm_last_error(const lbm_ctx* ctx);
 int lbm_set_wall_params(lbm_ctx* ctx, int inst, int mode, double F, double P0,
                         const double* k_per_segment, int n_seg);
 
+/* Local slip ratio (the closing discussion of Sec. 5: F need not be global;
+ * the Sec. 2.3 relation ties it to the local Womersley number and
+ * Delta r / R).  F_per_segment[s] in [0, 1) replaces, for wall segment s of
+ * instance inst, the single F of the last lbm_set_wall_params call, which
+ * resets every segment to its F.  n_seg must cover every segment id present
+ * at the instance's fluid voxels; the array is copied.  Takes effect for
+ * the next step.  Errors: LBM_EINVAL. */
+int lbm_set_wall_F(lbm_ctx* ctx, int inst, const double* F_per_segment, int n_seg);
+
 /* Drive of iolet id of instance inst (Sec. 3).  value(t) = a0 (1 + amp
  * sin(2 pi t / period + phase)), t = steps since the instance's last
  * lbm_init_fields; amp = 0 gives a steady value (period is then ignored,

@@ -33,6 +33,7 @@ struct InstState {
     int mode = LBM_WALL_BOUNCEBACK;
     double F = 0.0, P0 = 1.0 / 3.0;
     std::vector<double> k;      // per segment
+    std::vector<double> Fseg;   // slip ratio per segment
     int64_t t0 = 0;
     std::vector<IoletParams> iolets;
     std::vector<uint8_t> iolet_set;
@@ -259,7 +260,7 @@ int sync_params(lbm_ctx* c) {
             const double ki = kinv[c->rec_k[j]];
             bq[j].c1 = ki / 3.0;
             bq[j].c0 = (1.0 / 3.0 - s.P0) * ki;
-            bq[j].F = s.F;
+            bq[j].F = s.Fseg[c->rec_k[j] - c->seg_off[c->rec_inst[j]]];
             bq[j].pad = 0.0;
         }
         rc = rc ? rc : upload(c, c->bq, bq.data(), c->rec_k.size() * sizeof(WallCoef));
@@ -556,6 +557,7 @@ int lbm_create_geometry(lbm_ctx** out, const lbm_instance_desc* inst, int n_inst
         const InstanceGeom& g = c->plan.inst[k];
         InstState& s = c->ist[k];
         s.k.assign(g.n_seg, 1.0);
+        s.Fseg.assign(g.n_seg, 0.0);
         s.iolets.assign(std::max(g.n_iolet, 0), IoletParams());
         s.iolet_set.assign(std::max(g.n_iolet, 0), 0);
         c->seg_off[k] = so;
@@ -690,6 +692,24 @@ int lbm_set_wall_params(lbm_ctx* c, int inst, int mode, double F, double P0,
     s.F = F;
     s.P0 = P0;
     for (int j = 0; j < g.n_seg; ++j) s.k[j] = k_per_segment[j];
+    s.Fseg.assign(g.n_seg, F);
+    c->params_dirty = true;
+    return LBM_OK;
+}
+
+int lbm_set_wall_F(lbm_ctx* c, int inst, const double* F_per_segment, int n_seg) {
+    int rc = check_inst(c, inst);
+    if (rc) return rc;
+    const InstanceGeom& g = c->plan.inst[inst];
+    if (n_seg < g.n_seg || !F_per_segment)
+        return fail(c, LBM_EINVAL, "instance %d uses %d segments, got %d slip ratios", inst,
+                    g.n_seg, n_seg);
+    for (int s = 0; s < g.n_seg; ++s)
+        if (!(F_per_segment[s] >= 0.0 && F_per_segment[s] < 1.0))
+            return fail(c, LBM_EINVAL, "F of segment %d must lie in [0, 1) (got %g)", s,
+                        F_per_segment[s]);
+    InstState& s = c->ist[inst];
+    for (int j = 0; j < g.n_seg; ++j) s.Fseg[j] = F_per_segment[j];
     c->params_dirty = true;
     return LBM_OK;
 }

@@ -31,7 +31,7 @@ EXPORTS = [
     "lbm_get_stream", "lbm_time_steps", "lbm_read_fields", "lbm_read_populations",
     "lbm_write_populations", "lbm_cycle_delta", "lbm_get_info", "lbm_instance_sites",
     "lbm_set_launch", "lbm_autotune", "lbm_plan_export", "lbm_copy_probe",
-    "lbm_plan_compressed",
+    "lbm_plan_compressed", "lbm_set_wall_F",
 ]
 
 
@@ -90,6 +90,7 @@ def load():
         "lbm_create_geometry": [P, P, I, I, D],
         "lbm_destroy": [P],
         "lbm_set_wall_params": [P, I, I, D, D, P, I],
+        "lbm_set_wall_F": [P, I, P, I],
         "lbm_set_iolet": [P, I, I, I, D, D, D, D, P],
         "lbm_init_fields": [P, I, P, P],
         "lbm_init_fields_device": [P, I, P],
@@ -163,6 +164,11 @@ def lbm_destroy(ctx):
 def lbm_set_wall_params(ctx, inst, mode, F, P0, k):
     k = np.ascontiguousarray(np.atleast_1d(k), dtype=np.float64)
     _check(load().lbm_set_wall_params(ctx, inst, mode, float(F), float(P0), _p(k), len(k)), ctx)
+
+
+def lbm_set_wall_F(ctx, inst, F):
+    F = np.ascontiguousarray(np.atleast_1d(F), dtype=np.float64)
+    _check(load().lbm_set_wall_F(ctx, inst, _p(F), len(F)), ctx)
 
 
 def lbm_set_iolet(ctx, inst, iolet_id, kind, a0, amp=0.0, period=1.0, phase=0.0, direction=None):
@@ -331,6 +337,10 @@ class Lattice:
 
     def set_wall(self, inst, mode, F=0.0, P0=1.0 / 3.0, k=(1.0,)):
         lbm_set_wall_params(self.ctx, inst, mode, F, P0, k)
+
+    def set_wall_F(self, inst, F):
+        """Slip ratio per wall segment of instance inst (after set_wall)."""
+        lbm_set_wall_F(self.ctx, inst, F)
 
     def set_iolet(self, inst, iolet_id, kind, a0, amp=0.0, period=1.0, phase=0.0, direction=None):
         lbm_set_iolet(self.ctx, inst, iolet_id, kind, a0, amp, period, phase, direction)

@@ -15,7 +15,7 @@ All use D3Q19 BGK with tau = 0.8 and lattice units.
 from __future__ import annotations
 
 import dataclasses
-from typing import Dict, List
+from typing import Dict, List, Optional
 
 import numpy as np
 
@@ -32,6 +32,7 @@ class InstanceParams:
     P0: float
     k: List[float]
     iolets: Dict[int, dict]
+    F_seg: Optional[List[float]] = None     # slip ratio per segment (else F)
 
 
 @dataclasses.dataclass
@@ -85,6 +86,8 @@ def apply(lat: lbm.Lattice, wl: Workload, init=True):
     # instances at the next initialisation or step, so initialise after
     for k, p in enumerate(wl.params):
         lat.set_wall(k, p.mode, F=p.F, P0=p.P0, k=p.k)
+        if p.F_seg is not None:
+            lat.set_wall_F(k, p.F_seg)
         for i, q in p.iolets.items():
             lat.set_iolet(k, i, q["kind"], q["a0"], q.get("amp", 0.0), q.get("period", 1.0),
                           q.get("phase", 0.0), q.get("direction"))

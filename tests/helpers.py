@@ -23,6 +23,7 @@ class Problem:
     iolets: Dict[int, dict] = dataclasses.field(default_factory=dict)
     rho0: Optional[np.ndarray] = None
     u0: Optional[np.ndarray] = None
+    F_seg: Optional[List[float]] = None     # slip ratio per segment
 
 
 def make_oracle(p: Problem) -> oracle.Oracle:
@@ -30,6 +31,8 @@ def make_oracle(p: Problem) -> oracle.Oracle:
     o = oracle.Oracle(g.labels, p.tau, segment=g.segment, normal=g.normal,
                       iolet_weight=g.iolet_weight)
     o.set_wall(p.mode, F=p.F, P0=p.P0, k=p.k)
+    if p.F_seg is not None:
+        o.set_wall_F(p.F_seg)
     for i, q in p.iolets.items():
         o.set_iolet(i, q["kind"], q["a0"], q.get("amp", 0.0), q.get("period", 1.0),
                     q.get("phase", 0.0), q.get("direction", (0.0, 0.0, 0.0)))
@@ -39,6 +42,8 @@ def make_oracle(p: Problem) -> oracle.Oracle:
 
 def configure(lat: lbm.Lattice, inst: int, p: Problem, init=True):
     lat.set_wall(inst, p.mode, F=p.F, P0=p.P0, k=p.k)
+    if p.F_seg is not None:
+        lat.set_wall_F(inst, p.F_seg)
     for i, q in p.iolets.items():
         lat.set_iolet(inst, i, q["kind"], q["a0"], q.get("amp", 0.0), q.get("period", 1.0),
                       q.get("phase", 0.0), q.get("direction"))

@@ -412,3 +412,41 @@ def test_wall_changes_mid_run(dtype):
         record(f"wall_change_{mode}_{F}", e, dtype=dtype, steps=steps)
         assert e["u"] <= TOL[dtype] and e["p"] <= TOL[dtype], (mode, F, k)
     lat.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_slip_ratio_per_segment(dtype):
+    """A local F (Sec. 5 discussion): the three wall segments of a random
+    box get F = 0.1, 0.5 and 0.9, then new values mid-run, on both sides."""
+    p = H.random_box_problem(1)
+    p.F_seg = [0.1, 0.5, 0.9]
+    lat = H.make_lattice([p], dtype)
+    o = H.make_oracle(p)
+    for F_seg, steps in (([0.1, 0.5, 0.9], 40), ([0.8, 0.0, 0.3], 40)):
+        lat.set_wall_F(0, F_seg)
+        o.set_wall_F(F_seg)
+        lat.step(steps)
+        o.step(steps)
+        e = H.errors(lat.read_fields(0), o.read(), P0=p.P0)
+        record(f"slip_per_segment_{F_seg}", e, dtype=dtype, steps=steps)
+        assert e["u"] <= 10 * TOL[dtype] and e["p"] <= TOL[dtype]
+    with pytest.raises(lbm.LbmError):
+        lat.set_wall_F(0, [0.5, 0.5, 1.0])
+    with pytest.raises(lbm.LbmError):
+        lat.set_wall_F(0, [0.5])
+    lat.close()
+
+
+def test_quarter_scale_tree_with_local_slip_ratio():
+    """The quarter-scale tree with one F per vessel from the Sec. 2.3
+    relation (M calibrated to the paper's F = 0.85 for its alpha = 3
+    cylinder of radius 50), 600 steps in FP32 against the oracle."""
+    from paper_2108_08783_amd import slip
+    p = _tree_problem(0.25)
+    M = slip.calibrate_M(0.85, 3.0, slip.dr_over_R(50.0))
+    p.F_seg = list(slip.segment_F(p.geo, M, period=400.0, nu=0.1))
+    g, r = run_pair(p, "f32", 600)
+    e = H.errors(g, r, P0=p.P0)
+    record("tree_quarter_local_F", e, dtype="f32", steps=600,
+           F_min=min(p.F_seg), F_max=max(p.F_seg))
+    assert e["u"] <= TOL["f32"] and e["p"] <= TOL["f32"]
