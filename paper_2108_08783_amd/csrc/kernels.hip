@@ -29,33 +29,51 @@ namespace {
 // 16 bits round to nearest even.
 template <int DT>
 struct Codec;
+//
+// The update kernel works on scale * h (sdec / senc): scaling by a power of
+// two commutes with every rounding, so carrying the FP16 scale through the
+// moments, the relaxation and the link rules gives the same bits as
+// unscaling on load and rescaling on store, without the two multiplies per
+// population.
 template <>
 struct Codec<LBM_F64> {
     using raw = double;
     using acc = double;
+    static constexpr acc scale = 1.0;
     __device__ static acc dec(raw v) { return v; }
     __device__ static raw enc(acc v) { return v; }
+    __device__ static acc sdec(raw v) { return v; }
+    __device__ static raw senc(acc v) { return v; }
 };
 template <>
 struct Codec<LBM_F32> {
     using raw = float;
     using acc = float;
+    static constexpr acc scale = 1.0f;
     __device__ static acc dec(raw v) { return v; }
     __device__ static raw enc(acc v) { return v; }
+    __device__ static acc sdec(raw v) { return v; }
+    __device__ static raw senc(acc v) { return v; }
 };
 template <>
 struct Codec<LBM_F16DEV> {
     using raw = uint16_t;
     using acc = float;
+    static constexpr acc scale = 1024.0f;
     __device__ static acc dec(raw v) {
         return (float)__builtin_bit_cast(_Float16, v) * (1.0f / 1024.0f);
     }
     __device__ static raw enc(acc v) { return __builtin_bit_cast(uint16_t, (_Float16)(v * 1024.0f)); }
+    __device__ static acc sdec(raw v) { return (float)__builtin_bit_cast(_Float16, v); }
+    __device__ static raw senc(acc v) { return __builtin_bit_cast(uint16_t, (_Float16)v); }
 };
 template <>
 struct Codec<LBM_BF16DEV> {
     using raw = uint16_t;
     using acc = float;
+    static constexpr acc scale = 1.0f;
+    __device__ static acc sdec(raw v) { return dec(v); }
+    __device__ static raw senc(acc v) { return enc(v); }
     __device__ static acc dec(raw v) { return __uint_as_float((uint32_t)v << 16); }
     __device__ static raw enc(acc v) {
         uint32_t b = __float_as_uint(v);
@@ -128,13 +146,13 @@ __device__ __forceinline__ void gather32(const typename Codec<DT>::raw* __restri
     using T = typename O::type;
     using raw = typename O::raw;
     const T npt = (T)np, xt = (T)x;
-    h[0] = Codec<DT>::dec(ld<raw, NTL>(O::ptr(A, xt * (T)sizeof(raw))));
+    h[0] = Codec<DT>::sdec(ld<raw, NTL>(O::ptr(A, xt * (T)sizeof(raw))));
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
         const int32_t di = d[i - 1];
         const bool redirect = di <= Sentinel<int32_t>::GHOST;
         const T e = redirect ? (T)dopp(i) * npt + xt : (T)i * npt + (T)(x + di);
-        h[i] = Codec<DT>::dec(ld<raw, NTL>(O::ptr(A, e * (T)sizeof(raw))));
+        h[i] = Codec<DT>::sdec(ld<raw, NTL>(O::ptr(A, e * (T)sizeof(raw))));
     }
 }
 
@@ -205,6 +223,104 @@ __device__ __forceinline__ void site_offsets(const StepArgs& a, int x, int32_t (
     }
 }
 
+// Pulled slots of site x as 32-bit byte offsets (every buffer below 2^31
+// bytes).  Plane i is read through its own base pointer
+//   P_i = A + (i np - c_ix - np - 1) s        (s = bytes per slot),
+// which may lie below A; the offsets are then never negative:
+//   fluid upstream site x - c_i = x + d:      (x + d + c_ix + np + 1) s,
+//   own opposite slot (plane opp(i), site x): (x + (opp(i) - i + 1) np + c_ix + 1) s.
+// With compressed addressing every direction of one lattice row (dy, dz)
+// shares one row offset, d + c_ix being the row's stretch entry, and a link
+// to a non-fluid voxel picks the opposite-slot offset with a bit-select on
+// the site's link mask: no branch and no per-direction index arithmetic.
+template <int DT>
+__device__ __forceinline__ uint32_t redirect_off(int i, uint32_t xr, uint32_t np) {
+    constexpr uint32_t S = sizeof(typename Codec<DT>::raw);
+    return xr + ((dopp(i) > i ? 2u * np : 0u) + (uint32_t)CX[i]) * S;
+}
+
+template <int DT, int ADDR, bool ALIGNED>
+__device__ __forceinline__ void pull_slots(const StepArgs& a, int x, uint32_t (&o)[18],
+                                           bool& ghost, int& rec) {
+    constexpr uint32_t S = sizeof(typename Codec<DT>::raw);
+    const uint32_t np = (uint32_t)a.np;
+    const uint32_t own = ((uint32_t)x + np + 1u) * S;   // fluid source in the site's own row
+    const uint32_t xr = ((uint32_t)x + 1u) * S;
+    if constexpr (ADDR == ADDR_COMP) {
+        // ALIGNED: the 64 lanes of the wavefront hold the 64 sites of one
+        // record, which is therefore loaded with scalar loads.
+        const int w = ALIGNED ? __builtin_amdgcn_readfirstlane(x >> 6) : (x >> 6);
+        const int l = x & 63;
+        const WfRec r = a.wf[w];
+        const uint64_t bit = 1ull << l, below = bit - 1ull;
+        int st = r.cur + __popcll(r.smask & (bit | below));
+        st = st < 0 ? 0 : st;
+        // lane-indexed tables are read as a uniform base plus a 32-bit offset
+        const int4* SP = (const int4*)((const char*)a.stretch + (uint64_t)((uint32_t)st * 32u));
+        const int4 s0 = SP[0], s1 = SP[1];
+        uint32_t nf = 0;
+        rec = -1;
+        if (r.imask & bit) {
+            rec = r.firr + __popcll(r.imask & below);
+            nf = *(const uint32_t*)((const char*)a.nfm + (uint64_t)((uint32_t)rec * 4u));
+        }
+        const int32_t D[8] = {s0.x, s0.y, s0.z, s0.w, s1.x, s1.y, s1.z, s1.w};
+        uint32_t row[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) row[k] = own + (uint32_t)D[k] * S;
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            const int rs = row_slot(i);
+            const uint32_t n = rs < 0 ? own : row[rs];
+            const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe((int)nf, i - 1, 1);
+            o[i - 1] = (m & redirect_off<DT>(i, xr, np)) | (~m & n);
+        }
+        ghost = (int32_t)nf < 0;
+        if (r.emask & bit) {
+            // a row of several fluid runs: the site's own 18 offsets (its
+            // non-fluid links are in its link mask as for any irregular site)
+            const int e = r.fexc + __popcll(r.emask & below);
+            const uint64_t eo = (uint32_t)e * 4u;
+#pragma unroll
+            for (int i = 1; i < Q; ++i) {
+                const int32_t v = *(const int32_t*)((const char*)(a.exc + (int64_t)(i - 1) * a.n_exc_pad) + eo);
+                o[i - 1] = v <= Sentinel<int32_t>::GHOST
+                               ? redirect_off<DT>(i, xr, np)
+                               : ((uint32_t)(x + v + CX[i]) + np + 1u) * S;
+            }
+        }
+    } else {
+        using I = typename std::conditional<ADDR == ADDR_T16, int16_t, int32_t>::type;
+        const I* nbr = (const I*)a.nbr;
+        ghost = false;
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            const I v = nbr[(int64_t)(i - 1) * a.np + x];
+            const bool sent = v == Sentinel<I>::BB || v == Sentinel<I>::GHOST;
+            o[i - 1] = sent ? redirect_off<DT>(i, xr, np)
+                            : ((uint32_t)(x + (int32_t)v + CX[i]) + np + 1u) * S;
+            ghost |= v == Sentinel<I>::GHOST;
+        }
+        rec = ghost ? a.bidx[x] : -1;
+    }
+}
+
+// scale * h_i(x, t) for all i through the per-plane bases of pull_slots.
+template <int DT, bool NTL>
+__device__ __forceinline__ void gather_slots(const typename Codec<DT>::raw* __restrict__ A,
+                                             int64_t np, int x, const uint32_t (&o)[18],
+                                             typename Codec<DT>::acc (&h)[Q]) {
+    using raw = typename Codec<DT>::raw;
+    constexpr int64_t S = sizeof(raw);
+    const char* base = (const char*)A;
+    h[0] = Codec<DT>::sdec(ld<raw, NTL>((const raw*)(base + (uint64_t)((uint32_t)x * (uint32_t)S))));
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const char* P = base + ((int64_t)i * np - CX[i] - np - 1) * S;
+        h[i] = Codec<DT>::sdec(ld<raw, NTL>((const raw*)(P + (uint64_t)o[i - 1])));
+    }
+}
+
 // ------------------------------------------------------------- physics ----
 // Sec. 2.1 eqs. Density and Momentum in deviation form: sum_i w_i = 1 and
 // sum_i w_i c_i = 0, so rho = 1 + sum h_i and rho u = sum h_i c_i.
@@ -213,8 +329,9 @@ struct Mom {
     acc drho, rho, ux, uy, uz;
 };
 
+// isc: 1 / scale when h holds scale * h (the moments are returned unscaled).
 template <typename acc>
-__device__ __forceinline__ Mom<acc> moments(const acc (&h)[Q]) {
+__device__ __forceinline__ Mom<acc> moments(const acc (&h)[Q], acc isc = (acc)1) {
     Mom<acc> m;
     acc s = h[0];
 #pragma unroll
@@ -222,9 +339,9 @@ __device__ __forceinline__ Mom<acc> moments(const acc (&h)[Q]) {
     const acc jx = (h[1] - h[2]) + (h[7] - h[8]) + (h[9] - h[10]) + (h[11] - h[12]) + (h[13] - h[14]);
     const acc jy = (h[3] - h[4]) + (h[7] - h[8]) - (h[9] - h[10]) + (h[15] - h[16]) + (h[17] - h[18]);
     const acc jz = (h[5] - h[6]) + (h[11] - h[12]) - (h[13] - h[14]) + (h[15] - h[16]) - (h[17] - h[18]);
-    m.drho = s;
-    m.rho = (acc)1 + s;
-    const acc inv = (acc)1 / m.rho;
+    m.drho = s * isc;
+    m.rho = (acc)1 + m.drho;
+    const acc inv = ((acc)1 / m.rho) * isc;
     m.ux = jx * inv;
     m.uy = jy * inv;
     m.uz = jz * inv;
@@ -234,15 +351,17 @@ __device__ __forceinline__ Mom<acc> moments(const acc (&h)[Q]) {
 // Sec. 2.1 eq. feq (standard 1/2 factors) minus w_i:
 // w_i (drho + rho (3 c.u + 9/2 (c.u)^2 - 3/2 u.u)).  Pairs (2k+1, 2k+2) are
 // opposite directions with c.u = +-cu_k.
+// sc: scale of the result (a power of two, folded into the weights).
 template <typename acc>
-__device__ __forceinline__ void heq(acc drho, acc rho, acc ux, acc uy, acc uz, acc (&e)[Q]) {
+__device__ __forceinline__ void heq(acc drho, acc rho, acc ux, acc uy, acc uz, acc (&e)[Q],
+                                    acc sc = (acc)1) {
     const acc r0 = drho - rho * (acc)1.5 * (ux * ux + uy * uy + uz * uz);
     const acc r3 = (acc)3 * rho, r45 = (acc)4.5 * rho;
-    e[0] = W<acc>::w0 * r0;
+    e[0] = (W<acc>::w0 * sc) * r0;
     const acc cu[9] = {ux, uy, uz, ux + uy, ux - uy, ux + uz, ux - uz, uy + uz, uy - uz};
 #pragma unroll
     for (int k = 0; k < 9; ++k) {
-        const acc w = k < 3 ? W<acc>::w1 : W<acc>::w2;
+        const acc w = (k < 3 ? W<acc>::w1 : W<acc>::w2) * sc;
         const acc p = r3 * cu[k];
         const acc q = r45 * cu[k] * cu[k] + r0;
         e[2 * k + 1] = w * (q + p);
@@ -335,7 +454,7 @@ constexpr bool hoist_records() { return !(DT == LBM_F16DEV || DT == LBM_BF16DEV)
 
 template <typename acc>
 __device__ __forceinline__ void apply_links(const StepArgs& a, int j, const Mom<acc>& m,
-                                            acc (&out)[Q], const BRec<acc>& r) {
+                                            acc (&out)[Q], const BRec<acc>& r, acc sc) {
     const uint32_t bw = r.bw, bi = r.bi;
     const uint32_t wmask = bw & 0x7FFFEu, imask = bi & 0x7FFFEu;
     const uint32_t inst = bw >> 19;
@@ -367,7 +486,8 @@ __device__ __forceinline__ void apply_links(const StepArgs& a, int j, const Mom<
     // and opposite directions differ only in the sign of c.u.  The value of
     // link i goes to slot opp(i); both slots of a pair are written from the
     // unmodified post-collision values.
-    const acc A = m.rho * (s - (acc)1), Bs = s + (acc)1;
+    // out holds sc * h (sc a power of two), so the link terms are scaled too
+    const acc A = m.rho * (s - (acc)1) * sc, Bs = s + (acc)1;
     const acc u2 = (acc)1.5 * (m.ux * m.ux + m.uy * m.uy + m.uz * m.uz);
     const acc cu[9] = {m.ux, m.uy, m.uz, m.ux + m.uy, m.ux - m.uy, m.ux + m.uz, m.ux - m.uz,
                        m.uy + m.uz, m.uy - m.uz};
@@ -383,28 +503,30 @@ __device__ __forceinline__ void apply_links(const StepArgs& a, int j, const Mom<
         if (wo) out[i] = oo + w * A * (t - p);
         if (ii | io) {  // iolet links (rare): general form
             if (ii)
-                out[o] = oi + heq_one<acc>(i, idr, ir, ix, iy, iz) -
-                         heq_one<acc>(i, m.drho, m.rho, m.ux, m.uy, m.uz);
+                out[o] = oi + heq_one<acc>(i, idr, ir, ix, iy, iz) * sc -
+                         heq_one<acc>(i, m.drho, m.rho, m.ux, m.uy, m.uz) * sc;
             if (io)
-                out[i] = oo + heq_one<acc>(o, idr, ir, ix, iy, iz) -
-                         heq_one<acc>(o, m.drho, m.rho, m.ux, m.uy, m.uz);
+                out[i] = oo + heq_one<acc>(o, idr, ir, ix, iy, iz) * sc -
+                         heq_one<acc>(o, m.drho, m.rho, m.ux, m.uy, m.uz) * sc;
         }
     }
 }
 
 // Collision and store of one site whose pre-collision deviations h are
-// gathered (moments, BGK, link rules, 19 coalesced stores).
+// gathered, in the codec's scaled domain (moments, BGK, link rules, 19
+// coalesced stores).
 template <int DT, bool SMALL>
 __device__ __forceinline__ void collide_store(const StepArgs& a, int x, bool ghost, int rec,
                                               typename Codec<DT>::acc (&h)[Q],
                                               BRec<typename Codec<DT>::acc> br) {
     using raw = typename Codec<DT>::raw;
     using acc = typename Codec<DT>::acc;
+    constexpr acc sc = Codec<DT>::scale;
     raw* __restrict__ B = (raw*)a.B;
-    const Mom<acc> m = moments(h);
+    const Mom<acc> m = moments(h, (acc)1 / sc);
     {
         acc e[Q];
-        heq(m.drho, m.rho, m.ux, m.uy, m.uz, e);
+        heq(m.drho, m.rho, m.ux, m.uy, m.uz, e, sc);
         const acc om = (acc)a.omega;
 #pragma unroll
         for (int i = 0; i < Q; ++i) h[i] = h[i] + om * (e[i] - h[i]);
@@ -412,15 +534,25 @@ __device__ __forceinline__ void collide_store(const StepArgs& a, int x, bool gho
     acc (&out)[Q] = h;
     if (ghost) {
         if constexpr (!hoist_records<DT>()) br = load_brec<acc>(a, rec);
-        apply_links<acc>(a, rec, m, out, br);
+        apply_links<acc>(a, rec, m, out, br, sc);
     }
     const bool nt = (a.nontemporal & 1) != 0;
-    using O = Off<DT, SMALL>;
-    using T = typename O::type;
-    const T npt = (T)a.np, xt = (T)x;
+    if constexpr (SMALL) {
+        // one lane offset, a uniform base per plane
+        const uint64_t xs = (uint32_t)x * (uint32_t)sizeof(raw);
 #pragma unroll
-    for (int i = 0; i < Q; ++i)
-        put(O::ptr(B, ((T)i * npt + xt) * (T)sizeof(raw)), Codec<DT>::enc(out[i]), nt);
+        for (int i = 0; i < Q; ++i) {
+            char* Bi = (char*)B + (int64_t)i * a.np * (int64_t)sizeof(raw);
+            put((raw*)(Bi + xs), Codec<DT>::senc(out[i]), nt);
+        }
+    } else {
+        using O = Off<DT, SMALL>;
+        using T = typename O::type;
+        const T npt = (T)a.np, xt = (T)x;
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+            put(O::ptr(B, ((T)i * npt + xt) * (T)sizeof(raw)), Codec<DT>::senc(out[i]), nt);
+    }
 }
 
 // One site: pull, BGK collision (Sec. 2.1 eq. LBE_SRT) and store.  A site
@@ -431,18 +563,29 @@ __device__ __forceinline__ void collide_store(const StepArgs& a, int x, bool gho
 template <int DT, int ADDR, bool ALIGNED, bool SMALL, bool NTL>
 __device__ __forceinline__ void update_site(const StepArgs& a, int x, bool from_boundary_blocks) {
     using acc = typename Codec<DT>::acc;
-    int32_t d[18];
+    using raw = typename Codec<DT>::raw;
     int rec;
-    site_offsets<ADDR, ALIGNED>(a, x, d, rec);
-    bool ghost = false;
-#pragma unroll
-    for (int i = 0; i < 18; ++i) ghost |= (d[i] == Sentinel<int32_t>::GHOST);
-    if (ghost && !from_boundary_blocks && !a.fused) return;
-    BRec<acc> br;
-    if constexpr (hoist_records<DT>())
-        if (ghost) br = load_brec<acc>(a, rec);
+    bool ghost;
     acc h[Q];
-    gather32<DT, SMALL, NTL>((const typename Codec<DT>::raw*)a.A, a.np, x, d, h);
+    BRec<acc> br;
+    if constexpr (SMALL) {
+        uint32_t o[18];
+        pull_slots<DT, ADDR, ALIGNED>(a, x, o, ghost, rec);
+        if (ghost && !from_boundary_blocks && !a.fused) return;
+        if constexpr (hoist_records<DT>())
+            if (ghost) br = load_brec<acc>(a, rec);
+        gather_slots<DT, NTL>((const raw*)a.A, a.np, x, o, h);
+    } else {
+        int32_t d[18];
+        site_offsets<ADDR, ALIGNED>(a, x, d, rec);
+        ghost = false;
+#pragma unroll
+        for (int i = 0; i < 18; ++i) ghost |= (d[i] == Sentinel<int32_t>::GHOST);
+        if (ghost && !from_boundary_blocks && !a.fused) return;
+        if constexpr (hoist_records<DT>())
+            if (ghost) br = load_brec<acc>(a, rec);
+        gather32<DT, SMALL, NTL>((const raw*)a.A, a.np, x, d, h);
+    }
     collide_store<DT, SMALL>(a, x, ghost, rec, h, br);
 }
 
