@@ -305,19 +305,57 @@ __device__ __forceinline__ void pull_slots(const StepArgs& a, int x, uint32_t (&
     }
 }
 
-// scale * h_i(x, t) for all i through the per-plane bases of pull_slots.
+// Raw buffer loads (gfx9 buffer descriptor: stride 0, byte range checked,
+// an out-of-range load returns 0).  The per-lane byte offset goes in a
+// vector register, the per-plane offset in a scalar one, so a plane costs
+// no vector instruction and no scalar base pair.  AUX 2: non-temporal.
+constexpr int BUF_DWORD3 = 0x00020000;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void* base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes,
+                                             BUF_DWORD3);
+}
+
+template <typename raw, int AUX>
+__device__ __forceinline__ raw buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    if constexpr (sizeof(raw) == 2)
+        return __builtin_bit_cast(raw, __builtin_amdgcn_raw_buffer_load_b16(r, (int)voff, (int)soff, AUX));
+    else if constexpr (sizeof(raw) == 4)
+        return __builtin_bit_cast(raw, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, AUX));
+    else
+        return __builtin_bit_cast(raw, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, AUX));
+}
+
+// scale * h_i(x, t) for all i, with the offsets of pull_slots.  16-bit
+// storage reads through one buffer descriptor that starts (np + 2) slots
+// below A, so plane i's scalar offset (i np - c_ix + 1) s is positive and the
+// descriptor range ends with A; wider storage reads through a 64-bit base
+// per plane (measured: the buffer form is 3 % faster for 16-bit storage and
+// 2 % slower for FP32, whose register count then drops it to 6 waves).
 template <int DT, bool NTL>
 __device__ __forceinline__ void gather_slots(const typename Codec<DT>::raw* __restrict__ A,
                                              int64_t np, int x, const uint32_t (&o)[18],
                                              typename Codec<DT>::acc (&h)[Q]) {
     using raw = typename Codec<DT>::raw;
-    constexpr int64_t S = sizeof(raw);
-    const char* base = (const char*)A;
-    h[0] = Codec<DT>::sdec(ld<raw, NTL>((const raw*)(base + (uint64_t)((uint32_t)x * (uint32_t)S))));
+    constexpr uint32_t S = sizeof(raw);
+    if constexpr (S == 2) {
+        constexpr int AUX = NTL ? 2 : 0;
+        const uint32_t n = (uint32_t)np;
+        const __amdgpu_buffer_rsrc_t r =
+            buffer_rsrc((const char*)A - (int64_t)(np + 2) * S, (20u * n + 2u) * S);
+        h[0] = Codec<DT>::sdec(buf_ld<raw, AUX>(r, (uint32_t)x * S, (n + 2u) * S));
 #pragma unroll
-    for (int i = 1; i < Q; ++i) {
-        const char* P = base + ((int64_t)i * np - CX[i] - np - 1) * S;
-        h[i] = Codec<DT>::sdec(ld<raw, NTL>((const raw*)(P + (uint64_t)o[i - 1])));
+        for (int i = 1; i < Q; ++i)
+            h[i] = Codec<DT>::sdec(
+                buf_ld<raw, AUX>(r, o[i - 1], ((uint32_t)i * n - (uint32_t)CX[i] + 1u) * S));
+    } else {
+        const char* base = (const char*)A;
+        h[0] = Codec<DT>::sdec(ld<raw, NTL>((const raw*)(base + (uint64_t)((uint32_t)x * S))));
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            const char* P = base + ((int64_t)i * np - CX[i] - np - 1) * (int64_t)S;
+            h[i] = Codec<DT>::sdec(ld<raw, NTL>((const raw*)(P + (uint64_t)o[i - 1])));
+        }
     }
 }
 
@@ -537,7 +575,7 @@ __device__ __forceinline__ void collide_store(const StepArgs& a, int x, bool gho
         apply_links<acc>(a, rec, m, out, br, sc);
     }
     const bool nt = (a.nontemporal & 1) != 0;
-    if constexpr (SMALL) {
+    if constexpr (SMALL && sizeof(raw) > 2) {
         // one lane offset, a uniform base per plane
         const uint64_t xs = (uint32_t)x * (uint32_t)sizeof(raw);
 #pragma unroll
