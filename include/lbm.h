@@ -128,9 +128,16 @@ typedef struct {
  * nodes; Sec. 2.3 link classification), allocates device memory on the
  * current HIP device and initialises every instance to rho = 1, u = 0 with
  * bounce-back walls.  tau is the BGK relaxation time (Sec. 2.1), tau > 1/2.
+ * Site order on the device: each instance is updated in raster order with
+ * its fast axis innermost.  The fast axis is x unless the instance's fluid
+ * voxels form clearly longer runs along y or z (lbm_fast_axis); then that
+ * axis is exchanged with x internally.  This changes nothing at the
+ * interface: every call takes and returns sites in canonical order and
+ * vectors and directions in the caller's frame.  The environment variable
+ * LBM_FAST_AXIS (x, y, z or auto) read here overrides the choice.
  * Errors: LBM_EINVAL (n_inst <= 0, tau <= 1/2, unknown dtype, no fluid
  * voxel, fluid on the border, a site touching two different iolets, more
- * than 2^31/19 sites), LBM_ENOMEM, LBM_EDEVICE. */
+ * than 2^31/19 sites, an invalid LBM_FAST_AXIS), LBM_ENOMEM, LBM_EDEVICE. */
 int lbm_create_geometry(lbm_ctx** out, const lbm_instance_desc* inst, int n_inst, int dtype,
                         double tau);
 
@@ -302,6 +309,15 @@ int lbm_plan_export(const lbm_instance_desc* inst, int n_inst, const int* wall_m
  * stats, or the check failed). */
 int lbm_plan_compressed(const lbm_instance_desc* inst, int n_inst, const int* wall_mode,
                         int64_t* stats);
+
+/* The fast axis lbm_create_geometry uses for each of n_inst instances:
+ * axis[k] = 0 keeps x, 1 exchanges x and y, 2 exchanges x and z.  The axis
+ * with the longest mean run of fluid voxels (fluid voxels per run of
+ * consecutive fluid voxels along it) is chosen when its mean run is at
+ * least 1.25 times that along x; LBM_FAST_AXIS overrides.  lbm_plan_export
+ * and lbm_plan_compressed describe the geometry as given, without the
+ * exchange.  No device call is made.  Errors: LBM_EINVAL. */
+int lbm_fast_axis(const lbm_instance_desc* inst, int n_inst, int* axis);
 
 #ifdef __cplusplus
 }

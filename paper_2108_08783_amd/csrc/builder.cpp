@@ -2,6 +2,7 @@
 #include "builder.hpp"
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <sstream>
@@ -491,5 +492,104 @@ template void build_device_nbr<int32_t>(const Plan&, const std::vector<int>&, in
                                         std::vector<int32_t>&);
 template void build_device_nbr<int16_t>(const Plan&, const std::vector<int>&, int64_t,
                                         std::vector<int16_t>&);
+
+
+int choose_fast_axis(const lbm_instance_desc& d, int forced) {
+    if (forced >= 0 && forced <= 2) return forced;
+    if (!d.labels || d.nx <= 0 || d.ny <= 0 || d.nz <= 0) return 0;
+    const int64_t nx = d.nx, ny = d.ny, nxy = nx * ny;
+    const int W = n_workers(nxy * d.nz);
+    std::vector<std::array<int64_t, 4>> acc(W, std::array<int64_t, 4>{0, 0, 0, 0});
+    parallel_chunks(d.nz, W, [&](int t, int64_t z0, int64_t z1) {
+        std::array<int64_t, 4>& a = acc[t];   // fluid, runs along x, y, z
+        for (int64_t z = z0; z < z1; ++z)
+            for (int64_t y = 0; y < ny; ++y) {
+                const uint8_t* L = d.labels + z * nxy + y * nx;
+                for (int64_t x = 0; x < nx; ++x) {
+                    if (L[x] != 1) continue;
+                    ++a[0];
+                    a[1] += x == 0 || L[x - 1] != 1;
+                    a[2] += y == 0 || L[x - nx] != 1;
+                    a[3] += z == 0 || L[x - nxy] != 1;
+                }
+            }
+    });
+    int64_t f = 0, r[3] = {0, 0, 0};
+    for (const auto& a : acc) {
+        f += a[0];
+        for (int k = 0; k < 3; ++k) r[k] += a[k + 1];
+    }
+    if (f == 0) return 0;
+    double mean[3];
+    for (int k = 0; k < 3; ++k) mean[k] = (double)f / (double)std::max<int64_t>(1, r[k]);
+    const int best = mean[2] > mean[1] ? 2 : 1;
+    return mean[best] >= 1.25 * mean[0] ? best : 0;
+}
+
+void swap_axes(const lbm_instance_desc& d, int axis, SwappedGeom& out) {
+    const int64_t nx = d.nx, ny = d.ny, nz = d.nz;
+    // new dimensions and the old coordinates of new voxel (x', y', z')
+    const int64_t mx = axis == 1 ? ny : nz, my = axis == 1 ? nx : ny, mz = axis == 1 ? nz : nx;
+    const int64_t nvox = nx * ny * nz;
+    out.labels.assign((size_t)nvox, 0);
+    if (d.segment) out.segment.assign((size_t)nvox, 0);
+    if (d.normal) out.normal.assign((size_t)nvox * 3, 0.0f);
+    if (d.iolet_weight) out.iolet_weight.assign((size_t)nvox, 0.0f);
+    const int W = n_workers(nvox);
+    parallel_chunks(mz, W, [&](int, int64_t z0, int64_t z1) {
+        for (int64_t zp = z0; zp < z1; ++zp)
+            for (int64_t yp = 0; yp < my; ++yp)
+                for (int64_t xp = 0; xp < mx; ++xp) {
+                    const int64_t x = axis == 1 ? yp : zp, y = axis == 1 ? xp : yp,
+                                  z = axis == 1 ? zp : xp;
+                    const int64_t o = (z * ny + y) * nx + x, v = (zp * my + yp) * mx + xp;
+                    out.labels[v] = d.labels[o];
+                    if (d.segment) out.segment[v] = d.segment[o];
+                    if (d.iolet_weight) out.iolet_weight[v] = d.iolet_weight[o];
+                    if (d.normal)
+                        for (int a = 0; a < 3; ++a) {
+                            const int src = a == 0 ? axis : (a == axis ? 0 : a);
+                            out.normal[3 * v + a] = d.normal[3 * o + src];
+                        }
+                }
+    });
+    out.desc.nx = (int32_t)mx;
+    out.desc.ny = (int32_t)my;
+    out.desc.nz = (int32_t)mz;
+    out.desc.labels = out.labels.data();
+    out.desc.segment = d.segment ? out.segment.data() : nullptr;
+    out.desc.normal = d.normal ? out.normal.data() : nullptr;
+    out.desc.iolet_weight = d.iolet_weight ? out.iolet_weight.data() : nullptr;
+}
+
+void site_map(const lbm_instance_desc& d, int axis, const SwappedGeom& sw,
+              std::vector<int32_t>& c2i) {
+    const int64_t nx = d.nx, ny = d.ny, nz = d.nz;
+    // canonical index of the first fluid voxel of every original row (y, z)
+    std::vector<int64_t> start((size_t)(ny * nz) + 1, 0);
+    for (int64_t r = 0; r < ny * nz; ++r) {
+        const uint8_t* L = d.labels + r * nx;
+        int64_t n = 0;
+        for (int64_t x = 0; x < nx; ++x) n += L[x] == 1;
+        start[r + 1] = start[r] + n;
+    }
+    c2i.assign((size_t)start[ny * nz], 0);
+    // internal order visits the voxels of one original row with increasing x
+    // (x is the slowest or the middle loop of the exchanged raster), so a
+    // counter per row gives each voxel's canonical rank within its row
+    std::vector<int64_t> cnt((size_t)(ny * nz), 0);
+    const int64_t mx = sw.desc.nx, my = sw.desc.ny, mz = sw.desc.nz;
+    int64_t j = 0;
+    for (int64_t zp = 0; zp < mz; ++zp)
+        for (int64_t yp = 0; yp < my; ++yp) {
+            const uint8_t* L = sw.labels.data() + (zp * my + yp) * mx;
+            for (int64_t xp = 0; xp < mx; ++xp) {
+                if (L[xp] != 1) continue;
+                const int64_t y = axis == 1 ? xp : yp, z = axis == 1 ? zp : xp;
+                const int64_t r = z * ny + y;
+                c2i[(size_t)(start[r] + cnt[r]++)] = (int32_t)j++;
+            }
+        }
+}
 
 }  // namespace lbm

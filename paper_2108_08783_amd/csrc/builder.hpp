@@ -45,6 +45,34 @@ struct Plan {
 // Returns an empty string on success, else the reason.
 std::string build_plan(const lbm_instance_desc* desc, int n_inst, Plan& plan);
 
+// Site order of an instance.  Sites are updated in raster order with x
+// fastest, and the compressed addressing and the boundary work favour long
+// runs of fluid voxels along that axis.  An instance whose fluid runs are
+// clearly longer along y or z (mean run at least 1.25 times that along x)
+// is therefore stored with that axis exchanged for x; the exchange is an
+// involution on positions, velocities and directions, applied at the C ABI.
+// Returns 0 (keep x), 1 (exchange x and y) or 2 (exchange x and z); forced
+// in {0, 1, 2} overrides the choice, -1 chooses.  An instance without
+// labels or with empty dimensions keeps 0 (build_plan reports it).
+int choose_fast_axis(const lbm_instance_desc& d, int forced);
+
+// The instance with axes x and `axis` exchanged, in owning arrays (desc
+// points into them; optional arrays stay NULL; normals have their
+// components exchanged too).
+struct SwappedGeom {
+    std::vector<uint8_t> labels;
+    std::vector<uint16_t> segment;
+    std::vector<float> normal, iolet_weight;
+    lbm_instance_desc desc{};
+};
+void swap_axes(const lbm_instance_desc& d, int axis, SwappedGeom& out);
+
+// c2i[canonical local site] = internal local site: canonical order is the
+// raster order (x fastest) of the fluid voxels of d, internal order the
+// raster order of the exchanged geometry (sw, built by swap_axes).
+void site_map(const lbm_instance_desc& d, int axis, const SwappedGeom& sw,
+              std::vector<int32_t>& c2i);
+
 // Irregular sites: every site with at least one non-fluid link, in site
 // order.  Each carries a boundary record; the records with elastic-wall or
 // iolet links (the boundary pass) are listed in `ghost`.  The wall mode per

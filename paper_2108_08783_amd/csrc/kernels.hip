@@ -830,6 +830,18 @@ __global__ void k_zero_u32(unsigned int* p, int n) {
     if (k < n) p[k] = 0u;
 }
 
+__global__ void k_permute_rho_u(const float* __restrict__ in, float* __restrict__ out,
+                                const int32_t* __restrict__ c2i, int n, int axis) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int64_t j = c2i[k];
+    const float* v = in + 4 * (int64_t)k;
+    float* w = out + 4 * j;
+    w[0] = v[0];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) w[1 + m] = v[1 + (m == 0 ? axis : (m == axis ? 0 : m))];
+}
+
 inline int cdiv(int64_t a, int b) { return (int)((a + b - 1) / b); }
 
 template <template <int, typename> class F, typename... Args>
@@ -957,6 +969,13 @@ hipError_t launch_copy(void* dst, const void* src, size_t bytes, int nt, hipStre
 
 hipError_t launch_zero_u32(unsigned int* p, int n, hipStream_t s) {
     hipLaunchKernelGGL(k_zero_u32, dim3(cdiv(n, 256)), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_permute_rho_u(const float* in, float* out, const int32_t* c2i, int n, int axis,
+                                hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_permute_rho_u, dim3(cdiv(n, 256)), dim3(256), 0, s, in, out, c2i, n, axis);
     return hipGetLastError();
 }
 

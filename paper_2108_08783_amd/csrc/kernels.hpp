@@ -137,6 +137,11 @@ hipError_t launch_init(int dtype, int ibits, const InitArgs& a, hipStream_t s);
 hipError_t launch_read_pop(int dtype, int ibits, const PopArgs& a, hipStream_t s);
 hipError_t launch_delta(int dtype, int ibits, const DeltaArgs& a, hipStream_t s);
 hipError_t launch_zero_u32(unsigned int* p, int n, hipStream_t s);
+// out[4 c2i[k] + m] = in[4 k + m'] for k < n: site k of a canonical-order
+// (rho, ux, uy, uz) array goes to internal site c2i[k], with velocity
+// components x and `axis` (1 or 2) exchanged.
+hipError_t launch_permute_rho_u(const float* in, float* out, const int32_t* c2i, int n, int axis,
+                                hipStream_t s);
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, int nt, hipStream_t s);
 
 }  // namespace lbm

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <limits>
 #include <map>
@@ -67,6 +68,10 @@ struct lbm_ctx {
     int64_t np = 0;
     std::vector<InstState> ist;
     std::vector<int> seg_off, iolet_off;
+    // site order: per instance the axis exchanged with x (0 none) and, for
+    // exchanged instances, canonical local site -> internal local site
+    std::vector<int> axis;
+    std::vector<std::vector<int32_t>> c2i;
     int n_iolet_slots = 0, n_k = 0;
     // device memory
     std::vector<DevBuf> owned;
@@ -387,12 +392,63 @@ size_t elem_size(int dtype) {
     return 0;
 }
 
+// Component of the caller's frame that internal component m holds when axes
+// x and `axis` are exchanged (an involution).
+inline int comp_src(int m, int axis) { return axis == 0 ? m : (m == 0 ? axis : (m == axis ? 0 : m)); }
+
+// Direction of the caller's frame whose velocity is internal direction i's
+// with the components exchanged (an involution on 0..18).
+int dir_swap(int i, int axis) {
+    if (axis == 0) return i;
+    const int v[3] = {CX[i], CY[i], CZ[i]};
+    const int w[3] = {v[comp_src(0, axis)], v[comp_src(1, axis)], v[comp_src(2, axis)]};
+    for (int j = 0; j < Q; ++j)
+        if (CX[j] == w[0] && CY[j] == w[1] && CZ[j] == w[2]) return j;
+    return -1;
+}
+
+// LBM_FAST_AXIS: "x", "y" or "z" forces the fast axis of every instance;
+// unset, empty or "auto" lets the library choose.  -2 for anything else.
+int forced_axis() {
+    const char* e = std::getenv("LBM_FAST_AXIS");
+    if (!e || !*e || !std::strcmp(e, "auto")) return -1;
+    if (!std::strcmp(e, "x")) return 0;
+    if (!std::strcmp(e, "y")) return 1;
+    if (!std::strcmp(e, "z")) return 2;
+    return -2;
+}
+
 int init_instance(lbm_ctx* c, int inst, const double* rho, const double* u, const float* rho_u_dev,
                   const double* f) {
     int rc = sync_tables(c);
     if (rc) return rc;
     const InstanceGeom& g = c->plan.inst[inst];
     const int64_t n = g.n;
+    // caller's order and frame -> internal
+    const int ax = c->axis[inst];
+    std::vector<double> prho, pu, pf;
+    if (ax) {
+        const std::vector<int32_t>& m = c->c2i[inst];
+        if (f) {
+            pf.resize((size_t)n * Q);
+            int dm[Q];
+            for (int i = 0; i < Q; ++i) dm[i] = dir_swap(i, ax);
+            for (int64_t k = 0; k < n; ++k)
+                for (int i = 0; i < Q; ++i) pf[(size_t)m[k] * Q + i] = f[(size_t)k * Q + dm[i]];
+            f = pf.data();
+        }
+        if (rho) {
+            prho.resize((size_t)n);
+            for (int64_t k = 0; k < n; ++k) prho[(size_t)m[k]] = rho[k];
+            rho = prho.data();
+        }
+        if (u) {
+            pu.resize((size_t)n * 3);
+            for (int64_t k = 0; k < n; ++k)
+                for (int a = 0; a < 3; ++a) pu[(size_t)m[k] * 3 + a] = u[3 * k + comp_src(a, ax)];
+            u = pu.data();
+        }
+    }
     InitArgs a;
     a.A = c->buf[c->step & 1];
     a.nbr = nbr_rd(c);
@@ -409,6 +465,18 @@ int init_instance(lbm_ctx* c, int inst, const double* rho, const double* u, cons
     rc = ensure_scratch(c, need);
     if (rc) return rc;
     double* s = (double*)c->scratch.p;
+    if (ax && rho_u_dev) {
+        // the device array is in the caller's order: permute it on the device
+        // (n * 16 bytes of permuted values, then n * 4 bytes of site map)
+        float* perm = (float*)c->scratch.p;
+        int32_t* map = (int32_t*)(perm + 4 * n);
+        HIP_TRY(c, hipMemcpyAsync(map, c->c2i[inst].data(), (size_t)n * 4, hipMemcpyHostToDevice,
+                                  c->stream));
+        hipError_t pe = launch_permute_rho_u(rho_u_dev, perm, map, (int)n, ax, c->stream);
+        if (pe != hipSuccess)
+            return fail(c, LBM_EDEVICE, "permute launch failed: %s", hipGetErrorString(pe));
+        a.rho_u = perm;
+    }
     if (f) {
         HIP_TRY(c, hipMemcpyAsync(s, f, (size_t)n * Q * 8, hipMemcpyHostToDevice, c->stream));
         a.f = s;
@@ -531,6 +599,14 @@ int lbm_plan_compressed(const lbm_instance_desc* inst, int n_inst, const int* wa
     return LBM_OK;
 }
 
+int lbm_fast_axis(const lbm_instance_desc* inst, int n_inst, int* axis) {
+    if (!inst || !axis || n_inst <= 0) return fail(nullptr, LBM_EINVAL, "invalid arguments");
+    const int forced = forced_axis();
+    if (forced == -2) return fail(nullptr, LBM_EINVAL, "LBM_FAST_AXIS must be x, y, z or auto");
+    for (int k = 0; k < n_inst; ++k) axis[k] = choose_fast_axis(inst[k], forced);
+    return LBM_OK;
+}
+
 int lbm_create_geometry(lbm_ctx** out, const lbm_instance_desc* inst, int n_inst, int dtype,
                         double tau) {
     if (!out) return fail(nullptr, LBM_EINVAL, "out is NULL");
@@ -538,9 +614,26 @@ int lbm_create_geometry(lbm_ctx** out, const lbm_instance_desc* inst, int n_inst
     if (!(tau > 0.5)) return fail(nullptr, LBM_EINVAL, "tau must exceed 1/2 (got %g)", tau);
     if (elem_size(dtype) == 0) return fail(nullptr, LBM_EINVAL, "unknown dtype %d", dtype);
     if (n_inst <= 0 || n_inst > 8191) return fail(nullptr, LBM_EINVAL, "n_inst out of range");
+    const int forced = forced_axis();
+    if (forced == -2) return fail(nullptr, LBM_EINVAL, "LBM_FAST_AXIS must be x, y, z or auto");
     lbm_ctx* c = new (std::nothrow) lbm_ctx();
     if (!c) return fail(nullptr, LBM_ENOMEM, "out of host memory");
-    std::string e = build_plan(inst, n_inst, c->plan);
+    // site order: instances whose fluid runs are longest along y or z are
+    // stored with that axis exchanged for x
+    std::vector<lbm_instance_desc> descs(inst, inst + n_inst);
+    std::vector<SwappedGeom> swapped((size_t)n_inst);
+    c->axis.assign((size_t)n_inst, 0);
+    c->c2i.resize((size_t)n_inst);
+    for (int k = 0; k < n_inst; ++k) {
+        const int a = choose_fast_axis(inst[k], forced);
+        if (!a || !inst[k].labels || inst[k].nx <= 0 || inst[k].ny <= 0 || inst[k].nz <= 0) continue;
+        c->axis[k] = a;
+        swap_axes(inst[k], a, swapped[k]);
+        descs[k] = swapped[k].desc;
+        site_map(inst[k], a, swapped[k], c->c2i[k]);
+    }
+    std::string e = build_plan(descs.data(), n_inst, c->plan);
+    swapped.clear();
     if (!e.empty()) {
         delete c;
         return fail(nullptr, LBM_EINVAL, "%s", e.c_str());
@@ -737,7 +830,7 @@ int lbm_set_iolet(lbm_ctx* c, int inst, int id, int kind, double a0, double amp,
         if (!dir) return fail(c, LBM_EINVAL, "velocity iolet needs a direction");
         const double nn = std::sqrt(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
         if (!(nn > 0.0)) return fail(c, LBM_EINVAL, "direction must be non-zero");
-        for (int a = 0; a < 3; ++a) q.dir[a] = dir[a];
+        for (int a = 0; a < 3; ++a) q.dir[a] = dir[comp_src(a, c->axis[inst])];
     }
     s.iolets[id] = q;
     s.iolet_set[id] = 1;
@@ -853,21 +946,39 @@ int lbm_read_fields(lbm_ctx* c, int inst, double* rho, double* u, double* wss, f
         e = launch_wall(c->dtype, 32, wa, c->stream);
         if (e != hipSuccess) return fail(c, LBM_EDEVICE, "wall read-out launch failed: %s", hipGetErrorString(e));
     }
-    std::vector<double> hr, hu;
+    // internal order and frame; exchanged instances go through host copies
+    const int ax = c->axis[inst];
+    std::vector<double> hr, hu, hw;
+    std::vector<float> hd;
     double* prho = rho;
     double* pu = u;
-    if (!prho) { hr.resize(n); prho = hr.data(); }
-    if (!pu) { hu.resize(3 * n); pu = hu.data(); }
+    double* pw = wss;
+    float* pd = wall_dr;
+    if (!prho || ax) { hr.resize(n); prho = hr.data(); }
+    if (!pu || ax) { hu.resize(3 * n); pu = hu.data(); }
+    if (wss && ax) { hw.resize(n); pw = hw.data(); }
+    if (wall_dr && ax) { hd.resize(n); pd = hd.data(); }
     HIP_TRY(c, hipMemcpyAsync(prho, s_rho, (size_t)n * 8, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipMemcpyAsync(pu, s_u, (size_t)n * 24, hipMemcpyDeviceToHost, c->stream));
-    if (wss) HIP_TRY(c, hipMemcpyAsync(wss, s_wss, (size_t)n * 8, hipMemcpyDeviceToHost, c->stream));
-    if (wall_dr) HIP_TRY(c, hipMemcpyAsync(wall_dr, s_dr, (size_t)n * 4, hipMemcpyDeviceToHost, c->stream));
+    if (wss) HIP_TRY(c, hipMemcpyAsync(pw, s_wss, (size_t)n * 8, hipMemcpyDeviceToHost, c->stream));
+    if (wall_dr) HIP_TRY(c, hipMemcpyAsync(pd, s_dr, (size_t)n * 4, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     for (int64_t k = 0; k < n; ++k)
         if (!std::isfinite(prho[k]) || !std::isfinite(pu[3 * k]) || !std::isfinite(pu[3 * k + 1]) ||
             !std::isfinite(pu[3 * k + 2]))
             return fail(c, LBM_EDIVERGED, "non-finite field at site %lld of instance %d (step %lld)",
                         (long long)k, inst, (long long)c->step);
+    if (ax) {
+        const std::vector<int32_t>& m = c->c2i[inst];
+        for (int64_t k = 0; k < n; ++k) {
+            const size_t j = (size_t)m[k];
+            if (rho) rho[k] = prho[j];
+            if (u)
+                for (int a = 0; a < 3; ++a) u[3 * k + a] = pu[3 * j + comp_src(a, ax)];
+            if (wss) wss[k] = pw[j];
+            if (wall_dr) wall_dr[k] = pd[j];
+        }
+    }
     return LBM_OK;
 }
 
@@ -884,8 +995,19 @@ int lbm_read_populations(lbm_ctx* c, int inst, double* f) {
               (double*)c->scratch.p};
     hipError_t e = launch_read_pop(c->dtype, 32, a, c->stream);
     if (e != hipSuccess) return fail(c, LBM_EDEVICE, "launch failed: %s", hipGetErrorString(e));
-    HIP_TRY(c, hipMemcpyAsync(f, c->scratch.p, (size_t)g.n * Q * 8, hipMemcpyDeviceToHost, c->stream));
+    const int ax = c->axis[inst];
+    std::vector<double> hf;
+    double* pf = f;
+    if (ax) { hf.resize((size_t)g.n * Q); pf = hf.data(); }
+    HIP_TRY(c, hipMemcpyAsync(pf, c->scratch.p, (size_t)g.n * Q * 8, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (ax) {
+        const std::vector<int32_t>& m = c->c2i[inst];
+        int dm[Q];
+        for (int i = 0; i < Q; ++i) dm[i] = dir_swap(i, ax);
+        for (int64_t k = 0; k < g.n; ++k)
+            for (int i = 0; i < Q; ++i) f[(size_t)k * Q + i] = pf[(size_t)m[k] * Q + dm[i]];
+    }
     return LBM_OK;
 }
 

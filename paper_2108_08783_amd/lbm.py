@@ -31,7 +31,7 @@ EXPORTS = [
     "lbm_get_stream", "lbm_time_steps", "lbm_read_fields", "lbm_read_populations",
     "lbm_write_populations", "lbm_cycle_delta", "lbm_get_info", "lbm_instance_sites",
     "lbm_set_launch", "lbm_autotune", "lbm_plan_export", "lbm_copy_probe",
-    "lbm_plan_compressed", "lbm_set_wall_F",
+    "lbm_plan_compressed", "lbm_set_wall_F", "lbm_fast_axis",
 ]
 
 
@@ -91,6 +91,7 @@ def load():
         "lbm_destroy": [P],
         "lbm_set_wall_params": [P, I, I, D, D, P, I],
         "lbm_set_wall_F": [P, I, P, I],
+        "lbm_fast_axis": [P, I, P],
         "lbm_set_iolet": [P, I, I, I, D, D, D, D, P],
         "lbm_init_fields": [P, I, P, P],
         "lbm_init_fields_device": [P, I, P],
@@ -301,6 +302,17 @@ def lbm_plan_compressed(geoms, wall_modes=None):
     del keep
     return dict(stretches=int(st[0]), irregular=int(st[1]), exceptional=int(st[2]),
                 records=int(st[3]))
+
+
+def lbm_fast_axis(geoms):
+    """Host-only: the axis each instance's sites are ordered along on the
+    device (0 x, 1 y, 2 z; see lbm_create_geometry)."""
+    lib = load()
+    arr, keep = _descs(geoms)
+    out = np.zeros(len(geoms), np.int32)
+    _check(lib.lbm_fast_axis(arr, len(geoms), _p(out)), None)
+    del keep
+    return [int(v) for v in out]
 
 
 # ------------------------------------------------------------------ wrapper --

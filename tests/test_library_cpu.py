@@ -167,3 +167,23 @@ def test_compressed_addressing_of_a_batch():
     n = lbm.lbm_plan_export(geos, wall_modes=[1] * len(geos), tables=False)["n_sites"]
     assert st["records"] * 64 >= n
     assert st["exceptional"] < 0.01 * st["irregular"]
+
+
+def test_fast_axis_follows_the_longest_fluid_runs(monkeypatch):
+    monkeypatch.delenv("LBM_FAST_AXIS", raising=False)
+    z_tube = inputs.cylinder(8, 64)             # runs of 64 along z, <= 16 along x
+    x_tube = inputs.straight_tube_x(8, 60)
+    duct = inputs.duct(12, 10, 11)              # no axis clearly longer
+    assert lbm.lbm_fast_axis([z_tube, x_tube, duct]) == [2, 0, 0]
+    g = inputs.Geometry(labels=np.ascontiguousarray(z_tube.labels.transpose(1, 0, 2)))
+    assert lbm.lbm_fast_axis([g]) == [1]       # the same tube along y
+
+
+def test_fast_axis_override(monkeypatch):
+    tube = inputs.cylinder(6, 30)
+    for name, want in (("x", 0), ("y", 1), ("z", 2), ("auto", 2)):
+        monkeypatch.setenv("LBM_FAST_AXIS", name)
+        assert lbm.lbm_fast_axis([tube, tube]) == [want, want]
+    monkeypatch.setenv("LBM_FAST_AXIS", "w")
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_fast_axis([tube])
