@@ -34,6 +34,31 @@ def _compile(src: str) -> str:
     return obj
 
 
+def device_asm(src: str = "kernels.hip") -> str:
+    """gfx950 assembly of one source (device code only), with the build's
+    flags; used to check register use and scratch of the kernels."""
+    import tempfile
+    with tempfile.TemporaryDirectory() as d:
+        out = os.path.join(d, "k.s")
+        cmd = [HIPCC] + [f for f in FLAGS if f != "-fPIC"] + [
+            "--cuda-device-only", "-S", "-x", "hip", os.path.join(CSRC, src), "-o", out]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"hipcc -S failed for {src}:\n{r.stderr}")
+        return open(out).read()
+
+
+def kernel_resources(asm: str) -> dict:
+    """{kernel symbol: {"vgpr": n, "sgpr": n, "scratch": bytes}} from the
+    .set directives of an assembly listing."""
+    import re
+    res = {}
+    for name, key, val in re.findall(r"\.set (\S+)\.(num_vgpr|numbered_sgpr|private_seg_size), (\d+)", asm):
+        k = {"num_vgpr": "vgpr", "numbered_sgpr": "sgpr", "private_seg_size": "scratch"}[key]
+        res.setdefault(name, {})[k] = int(val)
+    return res
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]

@@ -1,0 +1,32 @@
+"""Register use of the update kernel as compiled for gfx950 (no GPU needed:
+hipcc cross-compiles).  The default configuration (compressed addressing,
+32-bit offsets) must not use scratch memory, and 16-bit storage must fit the
+64 registers of 8 waves per SIMD: close to that limit the compiler's
+allocation can fall into spilling kilobytes per lane, which costs far more
+than any change that triggers it gains."""
+import re
+
+import pytest
+
+from paper_2108_08783_amd import build
+
+
+@pytest.fixture(scope="module")
+def resources():
+    return build.kernel_resources(build.device_asm("kernels.hip"))
+
+
+DTYPES = {0: "f64", 1: "f32", 2: "f16", 3: "bf16"}
+
+
+@pytest.mark.parametrize("dt", [0, 1, 2, 3])
+@pytest.mark.parametrize("ntl", [0, 1])
+def test_default_update_kernel_has_no_scratch(resources, dt, ntl):
+    # k_step<DT, compressed addressing, 32-bit offsets, non-temporal loads>
+    pat = re.compile(rf"k_stepILi{dt}ELi0ELb1ELb{ntl}E")
+    names = [n for n in resources if pat.search(n)]
+    assert len(names) == 1, names
+    r = resources[names[0]]
+    assert r["scratch"] == 0, (DTYPES[dt], r)
+    if dt in (2, 3):
+        assert r["vgpr"] <= 64, (DTYPES[dt], r)
