@@ -48,6 +48,14 @@ def womersley_number(radius, period, nu):
     return np.asarray(radius, float) * np.sqrt(2.0 * math.pi / period / nu)
 
 
+def womersley_shape(M, alpha, y):
+    """Radial shape of the oscillating axial velocity in an elastic tube,
+    1 - M J0(Lambda y) / J0(Lambda) with y = r / R (Sec. 2.2); M = 1 is the
+    rigid tube (no slip at y = 1)."""
+    lam = cmath.exp(0.75j * math.pi) * float(alpha)
+    return 1.0 - M * jv(0, lam * np.asarray(y, float)) / jv(0, lam)
+
+
 def F_ratio(M, alpha, dr_over_R):
     """The complex ratio w(R) / w(R - Delta r) of Sec. 2.3 (vectorised over
     alpha and dr_over_R; M may be complex)."""

@@ -30,7 +30,7 @@ from typing import Dict, List, Optional
 
 import numpy as np
 
-from . import inputs
+from . import inputs, slip
 from . import lbm
 
 # Sec. 2.4 (fluid and wall) and Table A1 (lattice spacing and time step)
@@ -164,6 +164,29 @@ def womersley(R: int = 50, mode: int = lbm.BOUNCEBACK, kp: float = 50.0, settle:
                            err_rel_phase=float(err.max() / max(np.abs(ua).max(), 1e-30)),
                            err_rel_amplitude=float(err.max() / centre_amp),
                            err_rms_amplitude=float(np.sqrt((err ** 2).mean()) / centre_amp)))
+    # shape fits (the paper's elastic comparison): the first harmonic of the
+    # simulated centre-plane profile against 1 - M J0(Lambda r/R)/J0(Lambda)
+    # with one fitted complex amplitude; M from the Sec. 2.3 relation at the
+    # paper's F for this cylinder (reading: extended wall R = r + 1/2), and
+    # the rigid shape (M = 1, wall at the equal-area radius) for contrast
+    u_arr = np.asarray(u_t)
+    u_hat_sim = 2.0 * (u_arr * e[:, None]).mean(axis=0)
+    fits = {}
+    M_el = slip.calibrate_M(F_WALL, c.alpha, slip.dr_over_R(c.R))
+    for name, M, Rw in (("elastic_model", M_el, c.R + 0.5), ("rigid_model", 1.0, R_eff)):
+        al = Rw * math.sqrt(omega / c.nu)
+        phi = slip.womersley_shape(M, al, r / Rw)
+        A = complex(np.vdot(phi, u_hat_sim) / np.vdot(phi, phi))
+        amp_f = float(np.abs(A * phi).max())
+        per = []
+        for k in range(5):
+            j = k * samples // 5
+            err = np.abs(u_t[j] - np.real(A * phi * np.exp(1j * omega * ts[j])))
+            per.append(float(err.max() / amp_f))
+        res = np.abs(u_hat_sim - A * phi)
+        fits[name] = dict(M=float(M), R_wall=float(Rw), alpha=float(al),
+                          err_max_rel_amplitude=max(per), phase_err_rel_amplitude=per,
+                          harmonic_rms_rel=float(np.sqrt((res ** 2).mean()) / amp_f))
     # centreline: axis sites of the central half of the tube against the
     # analytic centre value, same phases; and the axial profile of the
     # deviation in eight bins over the whole length (entrance effects)
@@ -179,7 +202,7 @@ def womersley(R: int = 50, mode: int = lbm.BOUNCEBACK, kp: float = 50.0, settle:
                 G_lattice=c.G, G_measured=abs(G_hat), R_eff=R_eff,
                 mode="elastic" if mode == lbm.ELASTIC else "rigid", dtype=dtype, settle_periods=settle,
                 seconds_settle=t_settle, glups=n * settle * c.period / t_settle / 1e9,
-                phases=phases, centreline_central_half_err_rel_amplitude=cl_err,
+                phases=phases, shape_fits=fits, centreline_central_half_err_rel_amplitude=cl_err,
                 centreline_err_by_length_eighth=cl_bins)
 
 

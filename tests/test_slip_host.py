@@ -100,3 +100,22 @@ def test_segment_F_on_a_cylinder_uses_its_radius():
     assert F[0] == pytest.approx(abs(complex(slip.F_ratio(0.8, a, 1.2 / 12.7))))
     with pytest.raises(ValueError):
         slip.segment_F(inputs.duct(4, 4, 4), 0.8, period=400.0, nu=0.1)
+
+
+def test_womersley_shape():
+    from paper_2108_08783_amd import verification
+    y = np.linspace(0, 1, 11)
+    for M in (0.5, 0.83, 0.9 + 0.05j):
+        sh = slip.womersley_shape(M, 3.0, y)
+        assert abs(sh[-1] - (1 - M)) < 1e-14                      # wall value
+        for x in (0.02, 0.1):                                      # F is its ratio
+            want = complex(slip.F_ratio(M, 3.0, x))
+            got = complex(slip.womersley_shape(M, 3.0, 1.0) / slip.womersley_shape(M, 3.0, 1 - x))
+            assert abs(got - want) < 1e-13
+    # M = 1 is the rigid profile up to a complex factor
+    R, nu = 20.0, 0.1
+    omega = (3.0 / R) ** 2 * nu
+    rig = verification.womersley_profile(y * R, R, omega, nu, 1e-6)
+    sh = slip.womersley_shape(1.0, 3.0, y)
+    ratio = rig[:-1] / sh[:-1]
+    assert np.abs(ratio / ratio[0] - 1).max() < 1e-10
