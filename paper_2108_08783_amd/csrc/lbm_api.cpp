@@ -162,6 +162,16 @@ void dfree(lbm_ctx* c, void* p) {
     (void)hipFree(p);
 }
 
+// Device buffer released on every exit path of the scope that owns it.
+struct ScopedDev {
+    lbm_ctx* c;
+    void* p = nullptr;
+    explicit ScopedDev(lbm_ctx* ctx) : c(ctx) {}
+    ScopedDev(const ScopedDev&) = delete;
+    ScopedDev& operator=(const ScopedDev&) = delete;
+    ~ScopedDev() { dfree(c, p); }
+};
+
 int ensure_scratch(lbm_ctx* c, size_t bytes) {
     if (c->scratch.bytes >= bytes) return LBM_OK;
     dfree(c, c->scratch.p);
@@ -890,17 +900,21 @@ int lbm_time_steps(lbm_ctx* c, int64_t n, double* ms) {
         rc = get_graph(c, (int)(c->step & 1), &ex);
         if (rc) return rc;
     }
-    hipEvent_t e0, e1;
-    HIP_TRY(c, hipEventCreate(&e0));
-    HIP_TRY(c, hipEventCreate(&e1));
-    HIP_TRY(c, hipEventRecord(e0, c->stream));
+    struct Events {  // destroyed on every exit path
+        hipEvent_t e[2] = {nullptr, nullptr};
+        ~Events() {
+            for (hipEvent_t x : e)
+                if (x) (void)hipEventDestroy(x);
+        }
+    } ev;
+    HIP_TRY(c, hipEventCreate(&ev.e[0]));
+    HIP_TRY(c, hipEventCreate(&ev.e[1]));
+    HIP_TRY(c, hipEventRecord(ev.e[0], c->stream));
     rc = run_steps(c, n);
-    HIP_TRY(c, hipEventRecord(e1, c->stream));
-    HIP_TRY(c, hipEventSynchronize(e1));
+    HIP_TRY(c, hipEventRecord(ev.e[1], c->stream));
+    HIP_TRY(c, hipEventSynchronize(ev.e[1]));
     float t = 0;
-    HIP_TRY(c, hipEventElapsedTime(&t, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    HIP_TRY(c, hipEventElapsedTime(&t, ev.e[0], ev.e[1]));
     *ms = t;
     return rc;
 }
@@ -1134,11 +1148,12 @@ int lbm_autotune(lbm_ctx* c, int steps_per_trial, double* best_rate) {
     }
     // save the state: both buffers and the clock
     const size_t pop_bytes = (size_t)Q * c->np * c->esize;
-    void* save0 = nullptr;
-    void* save1 = nullptr;
-    rc = dalloc(c, &save0, pop_bytes);
-    rc = rc ? rc : dalloc(c, &save1, pop_bytes);
+    ScopedDev s0(c), s1(c);
+    rc = dalloc(c, &s0.p, pop_bytes);
+    rc = rc ? rc : dalloc(c, &s1.p, pop_bytes);
     if (rc) return rc;
+    void* const save0 = s0.p;
+    void* const save1 = s1.p;
     int64_t clock_save[2];
     HIP_TRY(c, hipMemcpyAsync(save0, c->buf[0], pop_bytes, hipMemcpyDeviceToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(save1, c->buf[1], pop_bytes, hipMemcpyDeviceToDevice, c->stream));
@@ -1197,8 +1212,6 @@ int lbm_autotune(lbm_ctx* c, int steps_per_trial, double* best_rate) {
     HIP_TRY(c, hipMemcpyAsync(c->buf[1], save1, pop_bytes, hipMemcpyDeviceToDevice, c->stream));
     HIP_TRY(c, hipMemcpyAsync(c->clock, clock_save, sizeof(clock_save), hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
-    dfree(c, save0);
-    dfree(c, save1);
     c->step = step_save;
     if (rc) {
         lbm_set_launch(c, old_block, old_ibits, -1, old_xcd, old_nt, old_fused, old_spt);
