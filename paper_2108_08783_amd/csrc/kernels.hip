@@ -477,10 +477,17 @@ __device__ __forceinline__ BRec<acc> load_brec(const StepArgs& a, int j) {
     BRec<acc> r;
     r.bw = a.bwall[j];
     r.bi = a.bio[j];
-    const WallCoef q = a.bq[j];
-    r.c1 = (acc)q.c1;
-    r.c0 = (acc)q.c0;
-    r.F = (acc)q.F;
+    if constexpr (std::is_same<acc, float>::value) {
+        const WallCoefF q = a.bqf[j];
+        r.c1 = q.c1;
+        r.c0 = q.c0;
+        r.F = q.F;
+    } else {
+        const WallCoef q = a.bq[j];
+        r.c1 = (acc)q.c1;
+        r.c0 = (acc)q.c0;
+        r.F = (acc)q.F;
+    }
     return r;
 }
 

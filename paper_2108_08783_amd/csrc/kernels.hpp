@@ -34,6 +34,13 @@ struct WallCoef {
     double c1, c0, F, pad;
 };
 
+// The same in single precision, read by float accumulation: no conversion
+// after the load, so a load issued ahead of the gathers need not complete
+// before they are issued (and half the bytes).
+struct WallCoefF {
+    float c1, c0, F, pad;
+};
+
 struct StepArgs {
     const void* A;          // populations read (deviation f - w, SoA, plane stride np)
     void* B;                // populations written
@@ -54,6 +61,7 @@ struct StepArgs {
     const uint32_t* bwall;  // elastic wall link mask | inst << 19
     const uint32_t* bio;    // iolet link mask | iolet slot << 19
     const WallCoef* bq;     // elastic-wall coefficients per record
+    const WallCoefF* bqf;   // the same in single precision
     const float* bw;        // iolet profile weight
     const InstParams* ip;
     const IoletParams* iop;

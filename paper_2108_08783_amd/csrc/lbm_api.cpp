@@ -87,6 +87,7 @@ struct lbm_ctx {
     uint32_t* bio = nullptr;
     int32_t* bk = nullptr;
     WallCoef* bq = nullptr;
+    WallCoefF* bqf = nullptr;
     std::vector<int32_t> rec_k, rec_inst;  // per record: stiffness index, instance
     float* bw = nullptr;
     int64_t nb = 0, n_irr = 0;
@@ -279,6 +280,12 @@ int sync_params(lbm_ctx* c) {
             bq[j].pad = 0.0;
         }
         rc = rc ? rc : upload(c, c->bq, bq.data(), c->rec_k.size() * sizeof(WallCoef));
+        // single-precision copy (rounded to nearest, as a conversion on the
+        // device would round)
+        std::vector<WallCoefF> bqf(bq.size());
+        for (size_t j = 0; j < bq.size(); ++j)
+            bqf[j] = WallCoefF{(float)bq[j].c1, (float)bq[j].c0, (float)bq[j].F, 0.0f};
+        rc = rc ? rc : upload(c, c->bqf, bqf.data(), c->rec_k.size() * sizeof(WallCoefF));
     }
     if (rc) return rc;
     c->params_dirty = false;
@@ -322,6 +329,7 @@ StepArgs step_args(const lbm_ctx* c, int parity) {
     a.bwall = c->bwall;
     a.bio = c->bio;
     a.bq = c->bq;
+    a.bqf = c->bqf;
     a.bw = c->bw;
     a.ip = c->ip;
     a.iop = c->iop;
@@ -709,6 +717,7 @@ int lbm_create_geometry(lbm_ctx** out, const lbm_instance_desc* inst, int n_inst
         rc = rc ? rc : dalloc(c, (void**)&c->bio, ni * 4);
         rc = rc ? rc : dalloc(c, (void**)&c->bk, ni * 4);
         rc = rc ? rc : dalloc(c, (void**)&c->bq, std::max<int64_t>(1, ni) * sizeof(WallCoef));
+        rc = rc ? rc : dalloc(c, (void**)&c->bqf, std::max<int64_t>(1, ni) * sizeof(WallCoefF));
         c->rec_k.assign(bl.kidx.begin(), bl.kidx.end());
         c->rec_inst.resize(bl.wall.size());
         for (size_t j = 0; j < bl.wall.size(); ++j) c->rec_inst[j] = (int32_t)(bl.wall[j] >> 19);
