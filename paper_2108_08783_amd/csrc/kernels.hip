@@ -491,11 +491,6 @@ __device__ __forceinline__ BRec<acc> load_brec(const StepArgs& a, int j) {
     return r;
 }
 
-// With 32- and 64-bit storage the record is loaded before the gathers, so
-// its latency overlaps theirs; 16-bit storage has no registers to spare at 8
-// waves per SIMD and loads it where it is used.
-template <int DT>
-constexpr bool hoist_records() { return !(DT == LBM_F16DEV || DT == LBM_BF16DEV); }
 
 template <typename acc>
 __device__ __forceinline__ void apply_links(const StepArgs& a, int j, const Mom<acc>& m,
@@ -577,10 +572,7 @@ __device__ __forceinline__ void collide_store(const StepArgs& a, int x, bool gho
         for (int i = 0; i < Q; ++i) h[i] = h[i] + om * (e[i] - h[i]);
     }
     acc (&out)[Q] = h;
-    if (ghost) {
-        if constexpr (!hoist_records<DT>()) br = load_brec<acc>(a, rec);
-        apply_links<acc>(a, rec, m, out, br, sc);
-    }
+    if (ghost) apply_links<acc>(a, rec, m, out, br, sc);
     const bool nt = (a.nontemporal & 1) != 0;
     if constexpr (SMALL && sizeof(raw) > 2) {
         // one lane offset, a uniform base per plane
@@ -617,8 +609,10 @@ __device__ __forceinline__ void update_site(const StepArgs& a, int x, bool from_
         uint32_t o[18];
         pull_slots<DT, ADDR, ALIGNED>(a, x, o, ghost, rec);
         if (ghost && !from_boundary_blocks && !a.fused) return;
-        if constexpr (hoist_records<DT>())
-            if (ghost) br = load_brec<acc>(a, rec);
+        // the boundary record is loaded ahead of the gathers, so its latency
+        // overlaps theirs (its single-precision coefficients need no
+        // conversion, so nothing waits for it before the gathers issue)
+        if (ghost) br = load_brec<acc>(a, rec);
         gather_slots<DT, NTL>((const raw*)a.A, a.np, x, o, h);
     } else {
         int32_t d[18];
@@ -627,8 +621,7 @@ __device__ __forceinline__ void update_site(const StepArgs& a, int x, bool from_
 #pragma unroll
         for (int i = 0; i < 18; ++i) ghost |= (d[i] == Sentinel<int32_t>::GHOST);
         if (ghost && !from_boundary_blocks && !a.fused) return;
-        if constexpr (hoist_records<DT>())
-            if (ghost) br = load_brec<acc>(a, rec);
+        if (ghost) br = load_brec<acc>(a, rec);
         gather32<DT, SMALL, NTL>((const raw*)a.A, a.np, x, d, h);
     }
     collide_store<DT, SMALL>(a, x, ghost, rec, h, br);
