@@ -1101,7 +1101,8 @@ int lbm_get_info(const lbm_ctx* c, lbm_info* info) {
         info->bytes_per_site_model = 2.0 * Q * (double)c->esize + 48.0 / 64.0 +
                                      32.0 * (double)c->n_stretch / N +
                                      4.0 * (double)c->n_irr / N +
-                                     (8.0 + sizeof(WallCoef)) * (double)c->nb / N +
+                                     (8.0 + (c->dtype == LBM_F64 ? sizeof(WallCoef) : sizeof(WallCoefF))) *
+                                         (double)c->nb / N +
                                      72.0 * (double)c->n_exc / N;
     else
         info->bytes_per_site_model = 2.0 * Q * (double)c->esize + 18.0 * (c->ibits / 8) +
