@@ -11,6 +11,8 @@ kernel (algorithmic bytes 2 * 19 * 4 per site per step over the kernel's
 average duration, measured with HIP events on the library's stream), and the
 FP64 CPU oracle timed on a bounded sample of the same workload.  Secondary
 figures (FP16/BF16 storage, bounce-back vs elastic) ride in "secondary".
+``--workload tree`` or ``--workload sweep`` times one of those instead (for
+profiling them on their own; no oracle baseline then).
 """
 from __future__ import annotations
 
@@ -45,10 +47,29 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(dtype):
-    """HBM bytes per launch from the committed counter summary, if it was
-    taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "update_kernel_tube32_traffic.json")
+# the main workload: the headline tube, or the tree or the sweep (used to
+# profile those on their own)
+WORKLOADS = {
+    "tube": ("tube32", "elastic straight cylinder R=32 L=512, D3Q19 BGK tau=0.8, "
+                       "pulsatile parabolic velocity inlet 0.02(1+0.5 sin(2 pi t/4000)), "
+                       "density outlet, k log-uniform [1e-3,1e-1] seed 1, F=0.85"),
+    "tree": ("tree", "elastic Murray tree seed 3 (7,484,227 sites), D3Q19 BGK tau=0.8, "
+                     "pulsatile parabolic velocity inlet 0.02(1+0.5 sin(2 pi t/4000)), "
+                     "density outlets, k log-uniform [1e-3,1e-1] per segment, F=0.5"),
+    "sweep": ("sweep64", "64 elastic tubes and bifurcations seed 4 (19.7M sites), D3Q19 BGK "
+                         "tau=0.8, pulsatile velocity inlets, density outlets, F=0.5"),
+}
+
+
+def make_workload(name):
+    from paper_2108_08783_amd import workloads
+    return {"tube": workloads.tube32, "tree": workloads.tree, "sweep": workloads.sweep}[name]()
+
+
+def traffic_from_profiles(dtype, workload="tube"):
+    """HBM bytes per launch from the committed counter summary of that
+    workload, if it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"update_kernel_{WORKLOADS[workload][0]}_traffic.json")
     try:
         d = json.load(open(path))
     except (OSError, ValueError):
@@ -185,6 +206,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--dtype", default="f32")
+    ap.add_argument("--workload", default="tube", choices=sorted(WORKLOADS),
+                    help="main workload (default: the tube the headline is quoted on)")
     ap.add_argument("--launch", default=None,
                     help="JSON launch configuration instead of autotuning")
     ap.add_argument("--probe-copy", action="store_true",
@@ -206,13 +229,16 @@ def main():
     launch = json.loads(args.launch) if args.launch else None
     dtype = args.dtype
     tube = workloads.tube32()
-    main_run = gpu_run(tube, dtype, args.steps, args.warmup, launch=launch)
-    print(f"[bench] tube {dtype}: {main_run['mlups']:.0f} MLUPS, "
+    main_wl = tube if args.workload == "tube" else make_workload(args.workload)
+    main_run = gpu_run(main_wl, dtype, args.steps, args.warmup, launch=launch)
+    if main_wl is not tube:
+        del main_wl
+    print(f"[bench] {args.workload} {dtype}: {main_run['mlups']:.0f} MLUPS, "
           f"{main_run['launch_us']:.2f} us/step", file=sys.stderr, flush=True)
     n = main_run["n"]
     alg_bytes = 2 * 19 * BYTES_PER_POP[dtype] * n
     achieved = alg_bytes / (main_run["launch_us"] * 1e-6) / 1e9
-    tr = traffic_from_profiles(dtype)
+    tr = traffic_from_profiles(dtype, args.workload)
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=PEAK_GBS, unit="GB/s",
                     frac=round(achieved / PEAK_GBS, 4), traffic=tr)
 
@@ -251,7 +277,7 @@ def main():
               file=sys.stderr, flush=True)
 
     cpu = None
-    if not args.no_cpu:
+    if not args.no_cpu and args.workload == "tube":
         cpu = cpu_baseline(tube)
         print(f"[bench] oracle: {cpu['value']:.1f} MLUPS on {cpu['cores']} threads",
               file=sys.stderr, flush=True)
@@ -266,9 +292,7 @@ def main():
         ms_per_step=round(main_run["wall_s"] * 1e3 / args.steps, 5),
         higher_is_better=True, scaling="weak", vs_baseline=None, dtype=dtype,
         data="synthetic",
-        config=dict(workload="elastic straight cylinder R=32 L=512, D3Q19 BGK tau=0.8, "
-                             "pulsatile parabolic velocity inlet 0.02(1+0.5 sin(2 pi t/4000)), "
-                             "density outlet, k log-uniform [1e-3,1e-1] seed 1, F=0.85",
+        config=dict(workload=WORKLOADS[args.workload][1],
                     sites=n, boundary_sites=info["n_boundary"], storage=dtype,
                     index_bits=info["index_bits"], block=info["block_size"],
                     xcd_remap=info["xcd_remap"], nontemporal=info["nontemporal"],
