@@ -627,13 +627,17 @@ __device__ __forceinline__ void update_site(const StepArgs& a, int x, bool from_
     collide_store<DT, SMALL>(a, x, ghost, rec, h, br);
 }
 
-// 16-bit storage is latency-bound: 8 waves per SIMD (at the cost of a few
-// spilled registers) beats 6; 32/64-bit storage keeps the compiler's choice.
-template <int DT>
-constexpr int step_waves() { return (DT == LBM_F16DEV || DT == LBM_BF16DEV) ? 8 : 1; }
+// 16-bit storage is latency-bound: 8 waves per SIMD beats 6.  Only the
+// 32-bit offset variants fit the 64 registers of 8 waves; the 64-bit
+// variants (population buffers beyond 2 GiB) would spill, and they and
+// 32/64-bit storage keep the compiler's choice.
+template <int DT, bool SMALL>
+constexpr int step_waves() {
+    return (SMALL && (DT == LBM_F16DEV || DT == LBM_BF16DEV)) ? 8 : 1;
+}
 
 template <int DT, int ADDR, bool SMALL, bool NTL>
-__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(step_waves<DT>())))
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(step_waves<DT, SMALL>())))
 void k_step(StepArgs a) {
     const int b = blockIdx.x;
     if (b < a.n_int_blocks) {

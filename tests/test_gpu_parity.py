@@ -391,6 +391,50 @@ def test_full_size_sweep_parity_sampled():
         lat.close()
 
 
+# A population buffer of 2^31 bytes or more switches the update kernel to
+# 64-bit byte offsets.  A long cylinder (radius 48) placed first in the
+# context takes the buffer past that size for each storage type.
+_FILLER_L = {"f64": 2200, "f32": 4400, "f16": 8800, "bf16": 8800}
+_POP_BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
+
+
+@pytest.mark.parametrize("dtype,launch", [
+    ("f64", None), ("f32", None), ("f16", None), ("bf16", None),
+    ("f32", dict(index_bits=32, boundary_fused=0, nontemporal=0))])
+def test_population_buffers_beyond_2GiB(dtype, launch):
+    """Three random boxes (every link type; elastic and bounce-back walls)
+    packed after a 16-63M-site cylinder, so that their upper population
+    planes lie beyond 2 GiB and the update uses 64-bit offsets: 60 steps,
+    each box against the oracle over every site with the random-box bounds;
+    the cylinder's fields must stay finite."""
+    g = inputs.cylinder(48, _FILLER_L[dtype])
+    filler = H.Problem(geo=g, tau=0.7, mode=lbm.ELASTIC, F=0.6, P0=0.999 / 3.0, k=[1e-2],
+                       iolets={0: dict(kind=lbm.DENSITY, a0=1.001),
+                               1: dict(kind=lbm.DENSITY, a0=0.999)})
+    boxes = [H.random_box_problem(s, mode=m)
+             for s, m in ((21, lbm.ELASTIC), (22, lbm.ELASTIC), (23, lbm.BOUNCEBACK))]
+    lat = H.make_lattice([filler] + boxes, dtype)
+    assert lat.info()["n_sites"] * 19 * _POP_BYTES[dtype] >= 2 ** 31
+    if launch:
+        lat.set_launch(**launch)
+    steps = 60
+    lat.step(steps)
+    for k, p in enumerate(boxes, start=1):
+        o = H.make_oracle(p)
+        o.step(steps)
+        e = H.errors(lat.read_fields(k), o.read(), P0=p.P0)
+        record(f"beyond_2GiB_box{k}", e, dtype=dtype, steps=steps, launch=launch)
+        if dtype in TOL:
+            tol = TOL[dtype]
+            assert e["u"] <= 10 * tol and e["p"] <= tol and e["wss"] <= 100 * tol, k
+        else:
+            bound = {"f16": 1e-2, "bf16": 5e-2}[dtype]
+            assert e["u"] <= bound and e["p"] <= bound, k
+    rho, u, _, _ = lat.read_fields(0, wss=False, wall_dr=False)
+    assert np.isfinite(rho).all() and np.isfinite(u).all()
+    lat.close()
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_wall_changes_mid_run(dtype):
     """Wall parameters and modes changed between steps (new stiffness and
