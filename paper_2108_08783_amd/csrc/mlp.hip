@@ -9,6 +9,7 @@
 // W_l (out_l x in_l, row-major) followed by b_l (out_l).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <cstring>
 
@@ -26,50 +27,105 @@ __device__ __forceinline__ uint16_t f2bf(float v) {  // round to nearest even
     return (uint16_t)(b >> 16);
 }
 
+__device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
+__device__ __forceinline__ float dsilu(float z) {
+    const float s = 1.0f / (1.0f + __expf(-z));
+    return s * (1.0f + z * (1.0f - s));
+}
+
 // C[M x N] (+)= op(A)[M x K] op(B)[K x N]; op(A)(m,k) = transA ? A[k*lda+m]
 // : A[m*lda+k]; op(B)(k,n) = transB ? B[n*ldb+k] : B[k*ldb+n].  bf16
 // operands, FP32 accumulation and output.  Tile 64 x 64 per 256-thread
 // block, K staged through LDS in steps of 32, each wave computing a 32 x 32
-// quarter as 2 x 2 MFMA 16x16x32 tiles.
+// quarter as 2 x 2 MFMA 16x16x32 tiles.  Split K: block z covers
+// k in [z kchunk, (z + 1) kchunk) and writes slab z of C (M ldc floats
+// each); with one slab this is the plain product.
 constexpr int TM = 64, TN = 64, TK = 32, LDK = TK + 8;
 
+// Stages the 64 x 32 tile T[r][k] = src(r0 + r, k0 + k) into LDS, with
+// src(r, k) = kmajor ? S[k ld + r] : S[r ld + k] and zeros outside r < R,
+// k < ke.  With vec (16-byte aligned rows, checked by the caller) each
+// thread reads 8 consecutive elements with one load: 8 values of k of one
+// r, or (kmajor) 8 values of r of one k, scattered into the tile.
+template <bool kmajor>
+__device__ __forceinline__ void stage(uint16_t (&T)[64][LDK], const uint16_t* __restrict__ S,
+                                      int ld, int r0, int R, int k0, int ke, bool vec,
+                                      int t) {
+    if (!kmajor && vec) {
+        const int r = t >> 2, k = (t & 3) * 8;
+        const int gr = r0 + r, gk = k0 + k;
+        if (gr < R && gk + 8 <= ke) {
+            *(uint4*)&T[r][k] = *(const uint4*)(S + (int64_t)gr * ld + gk);
+        } else {
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                T[r][k + j] = (gr < R && gk + j < ke) ? S[(int64_t)gr * ld + gk + j] : (uint16_t)0;
+        }
+        return;
+    }
+    if (kmajor && vec) {
+        const int k = t >> 3, r = (t & 7) * 8;
+        const int gr = r0 + r, gk = k0 + k;
+        if (gk < ke && gr + 8 <= R) {
+            const uint4 v = *(const uint4*)(S + (int64_t)gk * ld + gr);
+            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                T[r + 2 * j][k] = (uint16_t)(w[j] & 0xFFFFu);
+                T[r + 2 * j + 1][k] = (uint16_t)(w[j] >> 16);
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                T[r + j][k] = (gk < ke && gr + j < R) ? S[(int64_t)gk * ld + gr + j] : (uint16_t)0;
+        }
+        return;
+    }
+#pragma unroll
+    for (int q = 0; q < (64 * TK) / 256; ++q) {
+        const int e = t + 256 * q;
+        const int r = kmajor ? e % 64 : e / TK, k = kmajor ? e / 64 : e % TK;
+        const int gr = r0 + r, gk = k0 + k;
+        uint16_t v = 0;
+        if (gr < R && gk < ke) v = kmajor ? S[(int64_t)gk * ld + gr] : S[(int64_t)gr * ld + gk];
+        T[r][k] = v;
+    }
+}
+
+// Epilogue (bias != null): C = acc + bias[n] and, when Aout != null,
+// Aout = bf16(silu(C)) at the same index (the fused bias and activation of a
+// forward layer).  One instantiation per operand layout, so each carries only
+// the staging it uses.
+template <int transA, int transB>
 __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const uint16_t* __restrict__ A,
-                                              int lda, int transA, const uint16_t* __restrict__ B,
-                                              int ldb, int transB, float* __restrict__ C, int ldc,
-                                              int accumulate) {
+                                              int lda, const uint16_t* __restrict__ B, int ldb,
+                                              float* __restrict__ C, int ldc,
+                                              int accumulate, int kchunk,
+                                              const float* __restrict__ bias,
+                                              uint16_t* __restrict__ Aout) {
     __shared__ __attribute__((aligned(16))) uint16_t As[TM][LDK];
     __shared__ __attribute__((aligned(16))) uint16_t Bs[TN][LDK];
     const int t = threadIdx.x;
     const int wave = t >> 6, lane = t & 63;
-    const int m0 = blockIdx.x * TM, n0 = blockIdx.y * TN;
+    // tiles in order of n within m: the blocks that share a row strip of op(A)
+    // run together, so its second read comes from L2
+    const int ntn = (N + TN - 1) / TN;
+    const int m0 = (int)(blockIdx.x / ntn) * TM, n0 = (int)(blockIdx.x % ntn) * TN;
+    const int64_t kz = (int64_t)blockIdx.z * kchunk;
+    const int kb = (int)kz, ke = (int)(kz + kchunk < K ? kz + kchunk : K);
+    C += (int64_t)blockIdx.z * M * ldc;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    const bool va = (((uintptr_t)A & 15) == 0) && ((lda & 7) == 0);
+    const bool vb = (((uintptr_t)B & 15) == 0) && ((ldb & 7) == 0);
     f32x4 acc[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < K; k0 += TK) {
-        // stage A (64 x 32) and B (32 x 64, stored n-major), zero outside
-#pragma unroll
-        for (int r = 0; r < (TM * TK) / 256; ++r) {
-            const int e = t + 256 * r;
-            int m, k;
-            if (transA) { k = e / TM; m = e % TM; } else { m = e / TK; k = e % TK; }
-            const int gm = m0 + m, gk = k0 + k;
-            uint16_t v = 0;
-            if (gm < M && gk < K) v = transA ? A[(int64_t)gk * lda + gm] : A[(int64_t)gm * lda + gk];
-            As[m][k] = v;
-        }
-#pragma unroll
-        for (int r = 0; r < (TN * TK) / 256; ++r) {
-            const int e = t + 256 * r;
-            int n, k;
-            if (transB) { n = e / TK; k = e % TK; } else { k = e / TN; n = e % TN; }
-            const int gn = n0 + n, gk = k0 + k;
-            uint16_t v = 0;
-            if (gn < N && gk < K) v = transB ? B[(int64_t)gn * ldb + gk] : B[(int64_t)gk * ldb + gn];
-            Bs[n][k] = v;
-        }
+    for (int k0 = kb; k0 < ke; k0 += TK) {
+        // A (64 x 32) and B (32 x 64, stored n-major), zero outside
+        stage<transA != 0>(As, A, lda, m0, M, k0, ke, va, t);
+        stage<transB == 0>(Bs, B, ldb, n0, N, k0, ke, vb, t);
         __syncthreads();
         const int row = lane & 15, kg = (lane >> 4) * 8;
         bf16x8 af[2], bfr[2];
@@ -95,26 +151,12 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const uint16_
                 const int gm = m0 + wm + 16 * a + rg + r, gn = n0 + wn + 16 * b + col;
                 if (gm < M && gn < N) {
                     float* p = C + (int64_t)gm * ldc + gn;
-                    *p = accumulate ? *p + acc[a][b][r] : acc[a][b][r];
+                    float v = accumulate ? *p + acc[a][b][r] : acc[a][b][r];
+                    if (bias) v += bias[gn];
+                    *p = v;
+                    if (Aout) Aout[(int64_t)gm * ldc + gn] = f2bf(silu(v));
                 }
             }
-}
-
-__device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
-__device__ __forceinline__ float dsilu(float z) {
-    const float s = 1.0f / (1.0f + __expf(-z));
-    return s * (1.0f + z * (1.0f - s));
-}
-
-// Z[n x c] += b; act: A = bf16(silu(Z)) (Z kept as the pre-activation),
-// else Y = Z (output layer).
-__global__ void k_bias_act(int64_t n, int c, float* __restrict__ Z, const float* __restrict__ bias,
-                           uint16_t* __restrict__ Aout, int act) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n * c) return;
-    const float z = Z[e] + bias[e % c];
-    Z[e] = z;
-    if (act) Aout[e] = f2bf(silu(z));
 }
 
 // dZ = dA * silu'(Zpre) (bf16 for the next GEMM, FP32 copy for the bias
@@ -148,6 +190,58 @@ __global__ __launch_bounds__(256) void k_colsum(int64_t n, int c, const float* _
         __syncthreads();
     }
     if (threadIdx.x == 0) db[j] = red[0];
+}
+
+// Column sums of rows [b rows, (b + 1) rows) of dZ [n x c] into part[b c + j]
+// (block b).  Thread t sums column t % c over every (256 / c)-th row of the
+// range; the partial sums of a column are then added in thread order.
+__global__ __launch_bounds__(256) void k_colsum_part(int64_t n, int c, int64_t rows,
+                                                     const float* __restrict__ dZ,
+                                                     float* __restrict__ part) {
+    __shared__ float red[256];
+    const int t = threadIdx.x, per = 256 / c;
+    const int64_t r0 = (int64_t)blockIdx.x * rows, r1 = min(n, r0 + rows);
+    float s = 0.f;
+    if (t < per * c) {
+        const int j = t % c;
+        for (int64_t i = r0 + t / c; i < r1; i += per) s += dZ[i * c + j];
+    }
+    red[t] = s;
+    __syncthreads();
+    if (t < c) {
+        float a = 0.f;
+        for (int q = 0; q < per; ++q) a += red[q * c + t];
+        part[(int64_t)blockIdx.x * c + t] = a;
+    }
+}
+
+// out[e] = sum over z < S of part[z count + e], in order of z.
+__global__ void k_reduce_slabs(int S, int64_t count, const float* __restrict__ part,
+                               float* __restrict__ out) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= count) return;
+    float a = 0.f;
+    for (int z = 0; z < S; ++z) a += part[(int64_t)z * count + e];
+    out[e] = a;
+}
+
+// out[j] = sum over z < S of part[z count + j] for few columns: block j,
+// thread t adds z = t, t + 256, ..., and the 256 partial sums meet in a fixed
+// tree (the order does not depend on scheduling).
+__global__ __launch_bounds__(256) void k_reduce_cols(int S, int count,
+                                                     const float* __restrict__ part,
+                                                     float* __restrict__ out) {
+    __shared__ float red[256];
+    const int j = blockIdx.x, t = threadIdx.x;
+    float a = 0.f;
+    for (int z = t; z < S; z += 256) a += part[(int64_t)z * count + j];
+    red[t] = a;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) red[t] += red[t + w];
+        __syncthreads();
+    }
+    if (t == 0) out[j] = red[0];
 }
 
 // Mean squared error over n x c entries with per-column weights:
@@ -207,6 +301,9 @@ __global__ void k_adam(int64_t n, float* __restrict__ p, uint16_t* __restrict__ 
 
 inline unsigned nb(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
+// blocks of k_gemm for an M x N product (one per 64 x 64 tile)
+inline unsigned tiles(int M, int N) { return nb(M, TM) * nb(N, TN); }
+
 
 struct Dims {
     int L;            // layers
@@ -233,6 +330,12 @@ bool valid(const mlp_shape* s) {
     return s && s->n_in > 0 && s->width > 0 && s->n_out > 0 && s->depth >= 1 && s->depth <= 6;
 }
 
+// every product of a pass over n samples has at most 2^31 - 1 tiles
+bool tiles_fit(const mlp_shape* s, int64_t n) {
+    const int w = std::max(s->width, std::max(s->n_in, s->n_out));
+    return (int64_t)nb(n, TM) * nb(w, TN) <= INT32_MAX;
+}
+
 thread_local char g_err[256] = "";
 
 int err(const char* m) {
@@ -244,6 +347,46 @@ int check(hipError_t e) {
     if (e == hipSuccess) return 0;
     std::strncpy(g_err, hipGetErrorString(e), sizeof(g_err) - 1);
     return -3;
+}
+
+// Weight gradient C [M x N] = A^T B over K samples (A: K x M, B: K x N, bf16
+// row-major).  Its output is only M x N, so the K range is split over up to
+// 512 blocks of z, whose slabs (in work, work_floats floats) are then added
+// in slab order: the result does not depend on scheduling.  Few samples take
+// the plain product.
+int gemm_tn_split(int M, int N, int64_t K, const uint16_t* A, int lda, const uint16_t* B, int ldb,
+                  float* C, float* work, int64_t work_floats, hipStream_t st) {
+    const int64_t slab = (int64_t)M * N;
+    int64_t S = std::min<int64_t>(512, K / 8192);
+    S = std::min<int64_t>(S, work_floats / slab);
+    if (S <= 1) {
+        hipLaunchKernelGGL((k_gemm<1, 0>), dim3(tiles(M, N)), dim3(256), 0, st, M, N, (int)K, A,
+                           lda, B, ldb, C, N, 0, (int)K, nullptr, nullptr);
+        return check(hipGetLastError());
+    }
+    const int64_t kc = ((K + S - 1) / S + TK - 1) / TK * TK;
+    S = (K + kc - 1) / kc;
+    hipLaunchKernelGGL((k_gemm<1, 0>), dim3(tiles(M, N), 1, (unsigned)S), dim3(256), 0, st, M, N,
+                       (int)K, A, lda, B, ldb, work, N, 0, (int)kc, nullptr, nullptr);
+    hipLaunchKernelGGL(k_reduce_slabs, dim3(nb(slab, 256)), dim3(256), 0, st, (int)S, slab, work, C);
+    return check(hipGetLastError());
+}
+
+// Column sums of dZ [n x c] into db over up to 4096 row ranges, whose
+// partial sums (in work) are added in range order.
+int colsum_split(int64_t n, int c, const float* dZ, float* db, float* work, int64_t work_floats,
+                 hipStream_t st) {
+    if (c > 256) {
+        hipLaunchKernelGGL(k_colsum, dim3(c), dim3(256), 0, st, n, c, dZ, db);
+        return check(hipGetLastError());
+    }
+    int64_t B = std::min<int64_t>(4096, (n + 1023) / 1024);
+    B = std::max<int64_t>(1, std::min<int64_t>(B, work_floats / c));
+    const int64_t rows = (n + B - 1) / B;
+    B = (n + rows - 1) / rows;
+    hipLaunchKernelGGL(k_colsum_part, dim3((unsigned)B), dim3(256), 0, st, n, c, rows, dZ, work);
+    hipLaunchKernelGGL(k_reduce_cols, dim3(c), dim3(256), 0, st, (int)B, c, work, db);
+    return check(hipGetLastError());
 }
 
 }  // namespace
@@ -272,9 +415,21 @@ int mlp_gemm_bf16(int M, int N, int K, const uint16_t* A, int lda, int transA, c
                   int ldb, int transB, float* C, int ldc, int accumulate, void* stream) {
     if (M < 0 || N < 0 || K < 0 || !A || !B || !C) return err("mlp_gemm_bf16: bad arguments");
     if (M == 0 || N == 0) return 0;
-    dim3 grid(nb(M, TM), nb(N, TN));
-    hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, (hipStream_t)stream, M, N, K, A, lda, transA, B,
-                       ldb, transB, C, ldc, accumulate);
+    if ((int64_t)nb(M, TM) * nb(N, TN) > INT32_MAX) return err("mlp_gemm_bf16: too many tiles");
+    dim3 grid(tiles(M, N));
+    hipStream_t st = (hipStream_t)stream;
+    if (transA && transB)
+        hipLaunchKernelGGL((k_gemm<1, 1>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, C, ldc,
+                           accumulate, K, nullptr, nullptr);
+    else if (transA)
+        hipLaunchKernelGGL((k_gemm<1, 0>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, C, ldc,
+                           accumulate, K, nullptr, nullptr);
+    else if (transB)
+        hipLaunchKernelGGL((k_gemm<0, 1>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, C, ldc,
+                           accumulate, K, nullptr, nullptr);
+    else
+        hipLaunchKernelGGL((k_gemm<0, 0>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, C, ldc,
+                           accumulate, K, nullptr, nullptr);
     return check(hipGetLastError());
 }
 
@@ -283,20 +438,19 @@ int mlp_forward(const mlp_shape* s, const float* params, const uint16_t* wb, int
     if (!valid(s) || !params || !wb || !X || !Z || !A || n < 0)
         return err("mlp_forward: bad arguments");
     if (n == 0) return 0;
-    if (n > INT32_MAX) return err("mlp_forward: at most 2^31-1 samples per call");
+    if (n > INT32_MAX || !tiles_fit(s, n)) return err("mlp_forward: too many samples per call");
     const Dims d = dims(s);
     hipStream_t st = (hipStream_t)stream;
     const uint16_t* x = X;
     for (int l = 0; l < d.L; ++l) {
         const bool last = l == d.L - 1;
         float* Zl = Z + (int64_t)l * n * s->width;
-        int rc = mlp_gemm_bf16((int)n, d.out[l], d.in[l], x, d.in[l], 0, wb + d.woff[l], d.in[l], 1,
-                               Zl, d.out[l], 0, stream);
-        if (rc) return rc;
         uint16_t* Al = last ? nullptr : A + (int64_t)l * n * s->width;
-        hipLaunchKernelGGL(k_bias_act, dim3(nb(n * d.out[l], 256)), dim3(256), 0, st, n, d.out[l], Zl,
-                           params + d.boff[l], Al, last ? 0 : 1);
-        rc = check(hipGetLastError());
+        // Z_l = x W_l^T + b_l and A_l = bf16(silu(Z_l)) in the GEMM's epilogue
+        hipLaunchKernelGGL((k_gemm<0, 1>), dim3(tiles((int)n, d.out[l])), dim3(256), 0, st, (int)n,
+                           d.out[l], d.in[l], x, d.in[l], wb + d.woff[l], d.in[l], Zl, d.out[l], 0,
+                           d.in[l], params + d.boff[l], Al);
+        const int rc = check(hipGetLastError());
         if (rc) return rc;
         x = Al;
     }
@@ -308,7 +462,7 @@ int mlp_backward(const mlp_shape* s, const uint16_t* wb, int64_t n, const uint16
                  uint16_t* work_b, void* stream) {
     if (!valid(s) || !wb || !X || !Z || !A || !dY || !grad || !work_f || !work_b || n <= 0)
         return err("mlp_backward: bad arguments");
-    if (n > INT32_MAX) return err("mlp_backward: at most 2^31-1 samples per call");
+    if (n > INT32_MAX || !tiles_fit(s, n)) return err("mlp_backward: too many samples per call");
     const Dims d = dims(s);
     hipStream_t st = (hipStream_t)stream;
     const int L = d.L;
@@ -330,11 +484,12 @@ int mlp_backward(const mlp_shape* s, const uint16_t* wb, int64_t n, const uint16
         rc = check(hipGetLastError());
         if (rc) return rc;
         const uint16_t* prev = l == 0 ? X : A + (int64_t)(l - 1) * n * s->width;
-        // dW_l = dZ_l^T prev  (out x in), db_l = column sums of dZ_l
-        rc = mlp_gemm_bf16(out, in, (int)n, work_b, out, 1, prev, in, 0, grad + d.woff[l], in, 0, stream);
+        // dW_l = dZ_l^T prev  (out x in), db_l = column sums of dZ_l.  dA_l is
+        // consumed (dZ_l is in dZf and work_b), so its n x wmax floats hold
+        // the partial sums until dA_{l-1} is formed below.
+        rc = gemm_tn_split(out, in, n, work_b, out, prev, in, grad + d.woff[l], dA, n * wmax, st);
         if (rc) return rc;
-        hipLaunchKernelGGL(k_colsum, dim3(out), dim3(256), 0, st, n, out, dZf, grad + d.boff[l]);
-        rc = check(hipGetLastError());
+        rc = colsum_split(n, out, dZf, grad + d.boff[l], dA, n * wmax, st);
         if (rc) return rc;
         // dA_{l-1} = dZ_l W_l  (n x in)
         if (l > 0) {

@@ -185,3 +185,48 @@ class Net:
 
     def state(self):
         return self.params.detach().cpu().numpy().astype(np.float64)
+
+
+
+def flops_per_site(n_in=16, width=128, depth=4, n_out=4):
+    """Multiply-add flops of one forward pass per sample (2 per weight)."""
+    dims = [n_in] + [width] * depth + [n_out]
+    return 2 * sum(a * b for a, b in zip(dims[:-1], dims[1:]))
+
+
+def bench(n=7_484_227, reps=10, seed=0):
+    """Forward pass and training step of the default network on n samples
+    of random features, timed with HIP events on torch's current stream;
+    returns a dict of milliseconds and rates."""
+    import torch
+    net = Net(seed=seed)
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    X = net.to_bf16(torch.randn(n, net.shape.n_in, device="cuda", generator=g))
+    T = torch.randn(n, net.shape.n_out, device="cuda", generator=g)
+    out = dict(samples=n, flop_per_sample=flops_per_site())
+    for name, fn in (("forward", lambda: net.forward(X)),
+                     ("train_step", lambda: net.train_step(X, T, lr=1e-4))):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        flop = out["flop_per_sample"] * n * (1 if name == "forward" else 3)
+        out[name] = dict(ms=round(ms, 3), tflops=round(flop / (ms * 1e-3) / 1e12, 2))
+        print(f"[mlp] {name}: {ms:.3f} ms for {n} samples, {flop / (ms * 1e-3) / 1e12:.1f} TFLOP/s",
+              flush=True)
+    return out
+
+
+if __name__ == "__main__":
+    import argparse
+    import json
+    ap = argparse.ArgumentParser(description="time the warm-start network on one GPU")
+    ap.add_argument("--samples", type=int, default=7_484_227)
+    ap.add_argument("--reps", type=int, default=10)
+    a = ap.parse_args()
+    print(json.dumps(bench(a.samples, a.reps)), flush=True)

@@ -80,6 +80,28 @@ def test_backward_matches_reference():
             off += size
 
 
+def test_backward_with_split_sums_matches_reference_and_is_deterministic():
+    """40,000 samples: the weight-gradient products and the bias sums over
+    the samples are split into partial ranges (4 and 40) that are added in a
+    fixed order.  Against the reference, and bit-identical on a second call."""
+    import torch
+    n = 40000
+    net, p, X, Xb, d = _net_and_ref(n=n)
+    rng = np.random.default_rng(11)
+    dY = rng.normal(size=(n, 4))
+    net.forward(Xb)
+    g1 = net.backward(Xb, _t(dY, torch.float32)).cpu().numpy().copy()
+    g2 = net.backward(Xb, _t(dY, torch.float32)).cpu().numpy()
+    assert np.array_equal(g1, g2)
+    Yr, cache = M.forward(p, X, d)
+    gr = M.backward(p, cache, dY, d)
+    off = 0
+    for i, o in d:          # per tensor: W then b
+        for size in (i * o, o):
+            assert _rel(g1[off:off + size], gr[off:off + size]) <= 2e-2, (i, o, size)
+            off += size
+
+
 def test_loss_and_adam_match_reference():
     import torch
     from paper_2108_08783_amd import mlp
