@@ -47,13 +47,15 @@ int64_t mlp_act_bf16(const mlp_shape* s, int64_t n);
 
 /* C[M x N] (or C +=, if accumulate) = op(A) op(B) with op(A)(m,k) =
  * transA ? A[k*lda+m] : A[m*lda+k] and op(B)(k,n) = transB ? B[n*ldb+k] :
- * B[k*ldb+n]; bf16 operands, FP32 C (row-major, ldc). */
+ * B[k*ldb+n]; bf16 operands, FP32 C (row-major, ldc).  At most 2^31 - 1
+ * output tiles of 64 x 64 (else -1). */
 int mlp_gemm_bf16(int M, int N, int K, const uint16_t* A, int lda, int transA, const uint16_t* B,
                   int ldb, int transB, float* C, int ldc, int accumulate, void* stream);
 
 /* Forward pass of n samples X (n x n_in bf16, row-major): fills Z and A
  * (see mlp_act_*).  params: FP32 master (biases are read from it), wb:
- * bf16 copy (GEMM weights). */
+ * bf16 copy (GEMM weights).  n < 2^31 and at most 2^31 - 1 tiles of 64 x 64
+ * per layer product (else -1). */
 int mlp_forward(const mlp_shape* s, const float* params, const uint16_t* wb, int64_t n,
                 const uint16_t* X, float* Z, uint16_t* A, void* stream);
 
@@ -61,7 +63,10 @@ int mlp_forward(const mlp_shape* s, const float* params, const uint16_t* wb, int
  * pass that produced Z and A: writes the gradient of every parameter into
  * grad (FP32, parameter layout).  Workspaces: work_f of
  * 2 * n * max(width, n_out) floats and work_b of n * max(width, n_out)
- * bf16. */
+ * bf16.  The weight and bias gradients are sums over the samples: they are
+ * split into sample ranges whose partial sums (held in work_f) are added in
+ * a fixed order, so a repeated call gives bit-identical gradients.  Same
+ * limits on n as mlp_forward. */
 int mlp_backward(const mlp_shape* s, const uint16_t* wb, int64_t n, const uint16_t* X,
                  const float* Z, const uint16_t* A, const float* dY, float* grad, float* work_f,
                  uint16_t* work_b, void* stream);
