@@ -28,6 +28,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = ("MLUPS & % of HBM roofline (FP32 vs FP16 storage); cycles-to-periodic, warm vs cold")
 PEAK_GBS = 8000.0
+# autotuner trial length of the main run (the other runs use 256 steps)
+MAIN_TUNE_STEPS = 1024
 BYTES_PER_POP = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
 
 
@@ -110,7 +112,7 @@ def copy_probe(gib=1.0, reps=20):
     return out
 
 
-def gpu_run(wl, dtype, steps, warmup, bounceback=False, tune=True, launch=None):
+def gpu_run(wl, dtype, steps, warmup, bounceback=False, tune=True, launch=None, tune_steps=256):
     import torch
     from paper_2108_08783_amd import lbm, workloads
     tc = time.perf_counter()
@@ -122,7 +124,7 @@ def gpu_run(wl, dtype, steps, warmup, bounceback=False, tune=True, launch=None):
     if launch:
         lat.set_launch(**launch)
     elif tune:
-        lat.autotune(256)
+        lat.autotune(tune_steps)
     t_tune = time.perf_counter() - tc - t_create
     lat.step(warmup)
     lat.sync()
@@ -230,7 +232,8 @@ def main():
     dtype = args.dtype
     tube = workloads.tube32()
     main_wl = tube if args.workload == "tube" else make_workload(args.workload)
-    main_run = gpu_run(main_wl, dtype, args.steps, args.warmup, launch=launch)
+    main_run = gpu_run(main_wl, dtype, args.steps, args.warmup, launch=launch,
+                       tune_steps=MAIN_TUNE_STEPS)
     if main_wl is not tube:
         del main_wl
     print(f"[bench] {args.workload} {dtype}: {main_run['mlups']:.0f} MLUPS, "
@@ -275,6 +278,16 @@ def main():
             paper_elastic_s_per_1000=row["paper_elastic_s"], paper_cores=6000)
         print(f"[bench] paper cylinder R=100: {row['elastic_s']:.3f} s per 1000 iterations",
               file=sys.stderr, flush=True)
+        # the warm-start network on one sample per tree site: forward pass
+        # (bf16 MFMA; HBM-bound at 4,144 B per sample) and training step
+        from paper_2108_08783_amd import mlp
+        nb = mlp.bench(7_484_227, reps=5)
+        fwd_gbs = 4144 * nb["samples"] / (nb["forward"]["ms"] * 1e-3) / 1e9
+        secondary["mlp_7M_samples"] = dict(
+            nb, forward_achieved_gbs=round(fwd_gbs, 1),
+            forward_roofline_frac=round(fwd_gbs / PEAK_GBS, 4))
+        print(f"[bench] network: forward {nb['forward']['ms']:.2f} ms, training step "
+              f"{nb['train_step']['ms']:.2f} ms", file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu and args.workload == "tube":
@@ -297,7 +310,8 @@ def main():
                     index_bits=info["index_bits"], block=info["block_size"],
                     xcd_remap=info["xcd_remap"], nontemporal=info["nontemporal"],
                     boundary_fused=info["boundary_fused"],
-                    graph_steps=128, parallelism="single GPU", autotune_trial_steps=256),
+                    graph_steps=128, parallelism="single GPU",
+                    autotune_trial_steps=MAIN_TUNE_STEPS),
         roofline=roofline,
         cpu_baseline=cpu,
         secondary=secondary,

@@ -1195,18 +1195,19 @@ int lbm_autotune(lbm_ctx* c, int steps_per_trial, double* best_rate) {
                     }
         if (rc) break;
     }
-    // pass 2: the four fastest again, twice each with twice the steps
+    // pass 2: the six fastest again, three times each with twice the steps
+    // (single short trials are noisy: clocks and cache contents vary)
     if (!rc) {
         std::sort(cand.begin(), cand.end(),
                   [](const std::pair<double, TuneVal>& a, const std::pair<double, TuneVal>& b) {
                       return a.first < b.first;
                   });
-        const size_t top = std::min<size_t>(4, cand.size());
+        const size_t top = std::min<size_t>(6, cand.size());
         for (size_t k = 0; k < top && !rc; ++k) {
             const TuneVal& v = cand[k].second;
             rc = lbm_set_launch(c, v.block, v.ibits, -1, v.xcd, v.nt, v.fused, v.spt);
             double t = std::numeric_limits<double>::infinity();
-            for (int r = 0; r < 2 && !rc; ++r) {
+            for (int r = 0; r < 3 && !rc; ++r) {
                 double ms = 0;
                 rc = lbm_time_steps(c, 2 * steps_per_trial, &ms);
                 t = std::min(t, ms / 2.0);

@@ -10,6 +10,7 @@ from __future__ import annotations
 
 import ctypes
 import math
+import sys
 
 import numpy as np
 
@@ -218,7 +219,7 @@ def bench(n=7_484_227, reps=10, seed=0):
         flop = out["flop_per_sample"] * n * (1 if name == "forward" else 3)
         out[name] = dict(ms=round(ms, 3), tflops=round(flop / (ms * 1e-3) / 1e12, 2))
         print(f"[mlp] {name}: {ms:.3f} ms for {n} samples, {flop / (ms * 1e-3) / 1e12:.1f} TFLOP/s",
-              flush=True)
+              file=sys.stderr, flush=True)
     return out
 
 
