@@ -42,53 +42,71 @@ __device__ __forceinline__ float dsilu(float z) {
 // each); with one slab this is the plain product.
 constexpr int TM = 64, TN = 64, TK = 32, LDK = TK + 8;
 
-// Stages the 64 x 32 tile T[r][k] = src(r0 + r, k0 + k) into LDS, with
+// Staging of the 64 x 32 tile T[r][k] = src(r0 + r, k0 + k), with
 // src(r, k) = kmajor ? S[k ld + r] : S[r ld + k] and zeros outside r < R,
-// k < ke.  With vec (16-byte aligned rows, checked by the caller) each
-// thread reads 8 consecutive elements with one load: 8 values of k of one
-// r, or (kmajor) 8 values of r of one k, scattered into the tile.
+// k < ke: each thread loads 8 elements into registers (load_frag) and later
+// writes them into LDS (store_frag), so the next tile's loads are in flight
+// while the current one is multiplied.  With vec (16-byte aligned rows,
+// checked by the caller) the 8 elements are consecutive in memory: 8 values
+// of k of one r, or (kmajor) 8 values of r of one k; otherwise element q of
+// thread t is tile element t + 256 q.
+union Frag {
+    uint4 v;
+    uint16_t h[8];
+};
+
 template <bool kmajor>
-__device__ __forceinline__ void stage(uint16_t (&T)[64][LDK], const uint16_t* __restrict__ S,
-                                      int ld, int r0, int R, int k0, int ke, bool vec,
-                                      int t) {
-    if (!kmajor && vec) {
-        const int r = t >> 2, k = (t & 3) * 8;
-        const int gr = r0 + r, gk = k0 + k;
-        if (gr < R && gk + 8 <= ke) {
-            *(uint4*)&T[r][k] = *(const uint4*)(S + (int64_t)gr * ld + gk);
-        } else {
-#pragma unroll
-            for (int j = 0; j < 8; ++j)
-                T[r][k + j] = (gr < R && gk + j < ke) ? S[(int64_t)gr * ld + gk + j] : (uint16_t)0;
-        }
-        return;
-    }
-    if (kmajor && vec) {
-        const int k = t >> 3, r = (t & 7) * 8;
-        const int gr = r0 + r, gk = k0 + k;
-        if (gk < ke && gr + 8 <= R) {
-            const uint4 v = *(const uint4*)(S + (int64_t)gk * ld + gr);
-            const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                T[r + 2 * j][k] = (uint16_t)(w[j] & 0xFFFFu);
-                T[r + 2 * j + 1][k] = (uint16_t)(w[j] >> 16);
-            }
-        } else {
-#pragma unroll
-            for (int j = 0; j < 8; ++j)
-                T[r + j][k] = (gk < ke && gr + j < R) ? S[(int64_t)gk * ld + gr + j] : (uint16_t)0;
-        }
-        return;
-    }
-#pragma unroll
-    for (int q = 0; q < (64 * TK) / 256; ++q) {
+__device__ __forceinline__ void frag_pos(bool vec, int t, int q, int& r, int& k) {
+    if (vec && !kmajor) {
+        r = t >> 2;
+        k = (t & 3) * 8 + q;
+    } else if (vec) {
+        r = (t & 7) * 8 + q;
+        k = t >> 3;
+    } else {
         const int e = t + 256 * q;
-        const int r = kmajor ? e % 64 : e / TK, k = kmajor ? e / 64 : e % TK;
+        r = kmajor ? e % 64 : e / TK;
+        k = kmajor ? e / 64 : e % TK;
+    }
+}
+
+template <bool kmajor>
+__device__ __forceinline__ Frag load_frag(const uint16_t* __restrict__ S, int ld, int r0, int R,
+                                          int k0, int ke, bool vec, int t) {
+    Frag f;
+    if (vec) {
+        int r, k;
+        frag_pos<kmajor>(true, t, 0, r, k);
         const int gr = r0 + r, gk = k0 + k;
-        uint16_t v = 0;
-        if (gr < R && gk < ke) v = kmajor ? S[(int64_t)gk * ld + gr] : S[(int64_t)gr * ld + gk];
-        T[r][k] = v;
+        const bool whole = kmajor ? (gk < ke && gr + 8 <= R) : (gr < R && gk + 8 <= ke);
+        if (whole) {
+            f.v = kmajor ? *(const uint4*)(S + (int64_t)gk * ld + gr)
+                         : *(const uint4*)(S + (int64_t)gr * ld + gk);
+            return f;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        int r, k;
+        frag_pos<kmajor>(vec, t, q, r, k);
+        const int gr = r0 + r, gk = k0 + k;
+        f.h[q] = (gr < R && gk < ke) ? (kmajor ? S[(int64_t)gk * ld + gr] : S[(int64_t)gr * ld + gk])
+                                     : (uint16_t)0;
+    }
+    return f;
+}
+
+template <bool kmajor>
+__device__ __forceinline__ void store_frag(uint16_t (&T)[64][LDK], const Frag& f, bool vec, int t) {
+    if (vec && !kmajor) {
+        *(uint4*)&T[t >> 2][(t & 3) * 8] = f.v;
+        return;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        int r, k;
+        frag_pos<kmajor>(vec, t, q, r, k);
+        T[r][k] = f.h[q];
     }
 }
 
@@ -96,7 +114,7 @@ __device__ __forceinline__ void stage(uint16_t (&T)[64][LDK], const uint16_t* __
 // Aout = bf16(silu(C)) at the same index (the fused bias and activation of a
 // forward layer).  One instantiation per operand layout, so each carries only
 // the staging it uses.
-template <int transA, int transB>
+template <int transA, int transB, bool va, bool vb>
 __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const uint16_t* __restrict__ A,
                                               int lda, const uint16_t* __restrict__ B, int ldb,
                                               float* __restrict__ C, int ldc,
@@ -115,18 +133,24 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const uint16_
     const int kb = (int)kz, ke = (int)(kz + kchunk < K ? kz + kchunk : K);
     C += (int64_t)blockIdx.z * M * ldc;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-    const bool va = (((uintptr_t)A & 15) == 0) && ((lda & 7) == 0);
-    const bool vb = (((uintptr_t)B & 15) == 0) && ((ldb & 7) == 0);
     f32x4 acc[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    // A (64 x 32) and B (32 x 64, stored n-major) tiles, zero outside; the
+    // next pair is loaded while the current one is multiplied
+    constexpr bool ka = transA != 0, kbm = transB == 0;
+    Frag fa = load_frag<ka>(A, lda, m0, M, kb, ke, va, t);
+    Frag fb = load_frag<kbm>(B, ldb, n0, N, kb, ke, vb, t);
     for (int k0 = kb; k0 < ke; k0 += TK) {
-        // A (64 x 32) and B (32 x 64, stored n-major), zero outside
-        stage<transA != 0>(As, A, lda, m0, M, k0, ke, va, t);
-        stage<transB == 0>(Bs, B, ldb, n0, N, k0, ke, vb, t);
+        store_frag<ka>(As, fa, va, t);
+        store_frag<kbm>(Bs, fb, vb, t);
         __syncthreads();
+        if (k0 + TK < ke) {
+            fa = load_frag<ka>(A, lda, m0, M, k0 + TK, ke, va, t);
+            fb = load_frag<kbm>(B, ldb, n0, N, k0 + TK, ke, vb, t);
+        }
         const int row = lane & 15, kg = (lane >> 4) * 8;
         bf16x8 af[2], bfr[2];
 #pragma unroll
@@ -349,6 +373,28 @@ int check(hipError_t e) {
     return -3;
 }
 
+// 16-byte operand staging needs 16-byte aligned rows
+bool vec_ok(const void* p, int ld) { return (((uintptr_t)p & 15) == 0) && ((ld & 7) == 0); }
+
+template <int TA, int TB>
+void launch_gemm(dim3 grid, hipStream_t st, int M, int N, int K, const uint16_t* A, int lda,
+                 const uint16_t* B, int ldb, float* C, int ldc, int accumulate, int kchunk,
+                 const float* bias, uint16_t* Aout) {
+    const bool va = vec_ok(A, lda), vb = vec_ok(B, ldb);
+    if (va && vb)
+        hipLaunchKernelGGL((k_gemm<TA, TB, true, true>), grid, dim3(256), 0, st, M, N, K, A, lda,
+                           B, ldb, C, ldc, accumulate, kchunk, bias, Aout);
+    else if (va)
+        hipLaunchKernelGGL((k_gemm<TA, TB, true, false>), grid, dim3(256), 0, st, M, N, K, A, lda,
+                           B, ldb, C, ldc, accumulate, kchunk, bias, Aout);
+    else if (vb)
+        hipLaunchKernelGGL((k_gemm<TA, TB, false, true>), grid, dim3(256), 0, st, M, N, K, A, lda,
+                           B, ldb, C, ldc, accumulate, kchunk, bias, Aout);
+    else
+        hipLaunchKernelGGL((k_gemm<TA, TB, false, false>), grid, dim3(256), 0, st, M, N, K, A, lda,
+                           B, ldb, C, ldc, accumulate, kchunk, bias, Aout);
+}
+
 // Weight gradient C [M x N] = A^T B over K samples (A: K x M, B: K x N, bf16
 // row-major).  Its output is only M x N, so the K range is split over up to
 // 512 blocks of z, whose slabs (in work, work_floats floats) are then added
@@ -360,14 +406,14 @@ int gemm_tn_split(int M, int N, int64_t K, const uint16_t* A, int lda, const uin
     int64_t S = std::min<int64_t>(512, K / 8192);
     S = std::min<int64_t>(S, work_floats / slab);
     if (S <= 1) {
-        hipLaunchKernelGGL((k_gemm<1, 0>), dim3(tiles(M, N)), dim3(256), 0, st, M, N, (int)K, A,
-                           lda, B, ldb, C, N, 0, (int)K, nullptr, nullptr);
+        launch_gemm<1, 0>(dim3(tiles(M, N)), st, M, N, (int)K, A, lda, B, ldb, C, N, 0, (int)K,
+                          nullptr, nullptr);
         return check(hipGetLastError());
     }
     const int64_t kc = ((K + S - 1) / S + TK - 1) / TK * TK;
     S = (K + kc - 1) / kc;
-    hipLaunchKernelGGL((k_gemm<1, 0>), dim3(tiles(M, N), 1, (unsigned)S), dim3(256), 0, st, M, N,
-                       (int)K, A, lda, B, ldb, work, N, 0, (int)kc, nullptr, nullptr);
+    launch_gemm<1, 0>(dim3(tiles(M, N), 1, (unsigned)S), st, M, N, (int)K, A, lda, B, ldb, work, N,
+                      0, (int)kc, nullptr, nullptr);
     hipLaunchKernelGGL(k_reduce_slabs, dim3(nb(slab, 256)), dim3(256), 0, st, (int)S, slab, work, C);
     return check(hipGetLastError());
 }
@@ -419,17 +465,13 @@ int mlp_gemm_bf16(int M, int N, int K, const uint16_t* A, int lda, int transA, c
     dim3 grid(tiles(M, N));
     hipStream_t st = (hipStream_t)stream;
     if (transA && transB)
-        hipLaunchKernelGGL((k_gemm<1, 1>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, C, ldc,
-                           accumulate, K, nullptr, nullptr);
+        launch_gemm<1, 1>(grid, st, M, N, K, A, lda, B, ldb, C, ldc, accumulate, K, nullptr, nullptr);
     else if (transA)
-        hipLaunchKernelGGL((k_gemm<1, 0>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, C, ldc,
-                           accumulate, K, nullptr, nullptr);
+        launch_gemm<1, 0>(grid, st, M, N, K, A, lda, B, ldb, C, ldc, accumulate, K, nullptr, nullptr);
     else if (transB)
-        hipLaunchKernelGGL((k_gemm<0, 1>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, C, ldc,
-                           accumulate, K, nullptr, nullptr);
+        launch_gemm<0, 1>(grid, st, M, N, K, A, lda, B, ldb, C, ldc, accumulate, K, nullptr, nullptr);
     else
-        hipLaunchKernelGGL((k_gemm<0, 0>), grid, dim3(256), 0, st, M, N, K, A, lda, B, ldb, C, ldc,
-                           accumulate, K, nullptr, nullptr);
+        launch_gemm<0, 0>(grid, st, M, N, K, A, lda, B, ldb, C, ldc, accumulate, K, nullptr, nullptr);
     return check(hipGetLastError());
 }
 
@@ -447,9 +489,8 @@ int mlp_forward(const mlp_shape* s, const float* params, const uint16_t* wb, int
         float* Zl = Z + (int64_t)l * n * s->width;
         uint16_t* Al = last ? nullptr : A + (int64_t)l * n * s->width;
         // Z_l = x W_l^T + b_l and A_l = bf16(silu(Z_l)) in the GEMM's epilogue
-        hipLaunchKernelGGL((k_gemm<0, 1>), dim3(tiles((int)n, d.out[l])), dim3(256), 0, st, (int)n,
-                           d.out[l], d.in[l], x, d.in[l], wb + d.woff[l], d.in[l], Zl, d.out[l], 0,
-                           d.in[l], params + d.boff[l], Al);
+        launch_gemm<0, 1>(dim3(tiles((int)n, d.out[l])), st, (int)n, d.out[l], d.in[l], x, d.in[l],
+                          wb + d.woff[l], d.in[l], Zl, d.out[l], 0, d.in[l], params + d.boff[l], Al);
         const int rc = check(hipGetLastError());
         if (rc) return rc;
         x = Al;
