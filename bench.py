@@ -217,7 +217,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: the library runs on one GPU only (got --gpus {args.gpus}); "
-              "instances and domains would shard across GPUs as described in DESIGN.md",
+              "a batch would shard by instance and one large domain by site ranges with a "
+              "halo exchange, neither of which is built",
               file=sys.stderr)
         sys.exit(2)
     import torch
