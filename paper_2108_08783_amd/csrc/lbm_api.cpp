@@ -60,7 +60,7 @@ constexpr int GRAPH_STEPS = 128;  // even
 }  // namespace
 
 struct lbm_ctx {
-    std::string err;
+    mutable std::string err;  // last error (also set by the const queries)
     Plan plan;
     int dtype = LBM_F32;
     double tau = 1.0;
@@ -119,7 +119,7 @@ struct lbm_ctx {
 
 namespace {
 
-int fail(lbm_ctx* c, int code, const char* fmt, ...) {
+int fail(const lbm_ctx* c, int code, const char* fmt, ...) {
     char buf[1024];
     va_list ap;
     va_start(ap, fmt);
@@ -1113,7 +1113,8 @@ int lbm_get_info(const lbm_ctx* c, lbm_info* info) {
 
 int lbm_instance_sites(const lbm_ctx* c, int inst, int64_t* n) {
     if (!c || !n) return fail(nullptr, LBM_EINVAL, "NULL argument");
-    if (inst < 0 || inst >= (int)c->ist.size()) return fail(nullptr, LBM_EINVAL, "instance out of range");
+    if (inst < 0 || inst >= (int)c->ist.size())
+        return fail(c, LBM_EINVAL, "instance %d out of range [0, %zu)", inst, c->ist.size());
     *n = c->plan.inst[inst].n;
     return LBM_OK;
 }

@@ -435,6 +435,57 @@ def test_population_buffers_beyond_2GiB(dtype, launch):
     lat.close()
 
 
+def test_invalid_arguments_are_rejected_and_leave_the_context_usable():
+    """Every setter checks its arguments on the host before it changes any
+    state or launches anything: each invalid call below fails with a
+    message, and the context then runs the random box as before (against
+    the oracle after 60 steps)."""
+    p = H.random_box_problem(5)
+    nseg = p.geo.n_seg
+    assert nseg >= 2 and p.iolets
+    io = sorted(p.iolets)[0]
+    lat = H.make_lattice([p], "f32")
+    k_bad = list(p.k[:nseg])
+    k_bad[1] = -1.0
+    bad = {
+        "instance out of range": lambda: lat.set_wall(1, p.mode, F=p.F, P0=p.P0, k=p.k),
+        "wall mode": lambda: lat.set_wall(0, 7, F=p.F, P0=p.P0, k=p.k),
+        "F = 1": lambda: lat.set_wall(0, p.mode, F=1.0, P0=p.P0, k=p.k),
+        "P0 not finite": lambda: lat.set_wall(0, p.mode, F=p.F, P0=float("nan"), k=p.k),
+        "too few stiffness values": lambda: lat.set_wall(0, p.mode, F=p.F, P0=p.P0,
+                                                         k=p.k[:nseg - 1]),
+        "negative stiffness": lambda: lat.set_wall(0, p.mode, F=p.F, P0=p.P0, k=k_bad),
+        "too few slip ratios": lambda: lat.set_wall_F(0, [0.5] * (nseg - 1)),
+        "slip ratio 1.2": lambda: lat.set_wall_F(0, [0.5] * (nseg - 1) + [1.2]),
+        "iolet without fluid": lambda: lat.set_iolet(0, 40, lbm.DENSITY, 1.0),
+        "iolet kind": lambda: lat.set_iolet(0, io, 9, 1.0),
+        "density <= 0": lambda: lat.set_iolet(0, io, lbm.DENSITY, -1.0),
+        "pulsatile with period 0": lambda: lat.set_iolet(0, io, lbm.DENSITY, 1.0, amp=0.5,
+                                                         period=0.0),
+        "block size": lambda: lat.set_launch(block_size=96),
+        "index width": lambda: lat.set_launch(index_bits=8),
+        "negative step count": lambda: lat.step(-1),
+        "read-out of a missing instance": lambda: lat.read_fields(3),
+    }
+    for what, call in bad.items():
+        with pytest.raises(lbm.LbmError) as e:
+            call()
+        assert str(e.value), what
+    # the message is the failing call's own, also for the size query that
+    # precedes a read-out
+    with pytest.raises(lbm.LbmError, match="instance 3 out of range"):
+        lat.read_fields(3)
+    with pytest.raises(lbm.LbmError, match="block size 96"):
+        lat.set_launch(block_size=96)
+    lat.step(60)
+    o = H.make_oracle(p)
+    o.step(60)
+    e = H.errors(lat.read_fields(0), o.read(), P0=p.P0)
+    record("random_box_5_after_rejected_calls", e, dtype="f32", steps=60)
+    assert e["u"] <= 10 * TOL["f32"] and e["p"] <= TOL["f32"]
+    lat.close()
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_wall_changes_mid_run(dtype):
     """Wall parameters and modes changed between steps (new stiffness and
