@@ -261,8 +261,9 @@ def test_cycle_delta_monitor():
 def test_full_size_tube_parity():
     """The 1,640,960-site tube (R=32, L=512) in the benchmark's launch
     configuration (autotuned), from a non-equilibrium state, 1000 steps,
-    against one oracle run over every site: FP32 within 1e-5 on u and p;
-    FP16 and BF16 storage stated (bounded loosely)."""
+    against one oracle run over every site: FP64 storage to rounding
+    (1e-11), FP32 within 1e-5 on u and p; FP16 and BF16 storage stated
+    (bounded loosely)."""
     p = H.tube_problem(32, 512, seed=1, period=4000.0)
     rng = np.random.default_rng(12)
     n = p.geo.n_fluid
@@ -273,8 +274,9 @@ def test_full_size_tube_parity():
     o = H.make_oracle(p)
     o.step(steps)
     ref = o.read()
-    bound = {"f32": (1e-5, 1e-5), "f16": (5e-3, 5e-3), "bf16": (5e-2, 5e-2)}
-    for dtype in ("f32", "f16", "bf16"):
+    bound = {"f64": (1e-11, 1e-11), "f32": (1e-5, 1e-5), "f16": (5e-3, 5e-3),
+             "bf16": (5e-2, 5e-2)}
+    for dtype in ("f64", "f32", "f16", "bf16"):
         lat = H.make_lattice([p], dtype)
         lat.autotune(16)
         lat.step(steps)
@@ -296,7 +298,7 @@ def _tree_problem(scale, seed=3):
     return H.Problem(geo=g, tau=0.8, mode=lbm.ELASTIC, F=0.5, P0=1.0 / 3.0, k=k, iolets=io)
 
 
-@pytest.mark.parametrize("dtype", ["f32", "f16"])
+@pytest.mark.parametrize("dtype", ["f32", "f16", "bf16"])
 def test_quarter_scale_tree(dtype):
     """Quarter-scale Murray tree (about 105k sites, 79 stiffness segments,
     48 outlets), elastic walls, pulsatile inlet, 600 steps."""
@@ -304,7 +306,7 @@ def test_quarter_scale_tree(dtype):
     g, r = run_pair(p, dtype, 600)
     e = H.errors(g, r, P0=p.P0)
     record("tree_quarter", e, dtype=dtype, steps=600)
-    bound = {"f32": 1e-5, "f16": 1e-2}[dtype]
+    bound = {"f32": 1e-5, "f16": 1e-2, "bf16": 5e-2}[dtype]
     assert e["u"] <= bound and e["p"] <= bound
 
 
