@@ -55,6 +55,12 @@ union Frag {
     uint16_t h[8];
 };
 
+// LDS tiles hold row r's group of 8 k values g at group g ^ (r / 8 mod 4):
+// a thread that writes 8 rows of one k (k-major operands) then spreads over
+// 4 bank groups instead of one, and a group of 8 k stays 16-byte aligned
+// for the MFMA operand reads.
+__device__ __forceinline__ int swz(int r) { return ((r >> 3) & 3) << 3; }
+
 template <bool kmajor>
 __device__ __forceinline__ void frag_pos(bool vec, int t, int q, int& r, int& k) {
     if (vec && !kmajor) {
@@ -99,14 +105,15 @@ __device__ __forceinline__ Frag load_frag(const uint16_t* __restrict__ S, int ld
 template <bool kmajor>
 __device__ __forceinline__ void store_frag(uint16_t (&T)[64][LDK], const Frag& f, bool vec, int t) {
     if (vec && !kmajor) {
-        *(uint4*)&T[t >> 2][(t & 3) * 8] = f.v;
+        const int r = t >> 2;
+        *(uint4*)&T[r][((t & 3) * 8) ^ swz(r)] = f.v;
         return;
     }
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         int r, k;
         frag_pos<kmajor>(vec, t, q, r, k);
-        T[r][k] = f.h[q];
+        T[r][k ^ swz(r)] = f.h[q];
     }
 }
 
@@ -154,9 +161,15 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const uint16_
         const int row = lane & 15, kg = (lane >> 4) * 8;
         bf16x8 af[2], bfr[2];
 #pragma unroll
-        for (int a = 0; a < 2; ++a) af[a] = *(const bf16x8*)&As[wm + 16 * a + row][kg];
+        for (int a = 0; a < 2; ++a) {
+            const int m = wm + 16 * a + row;
+            af[a] = *(const bf16x8*)&As[m][kg ^ swz(m)];
+        }
 #pragma unroll
-        for (int b = 0; b < 2; ++b) bfr[b] = *(const bf16x8*)&Bs[wn + 16 * b + row][kg];
+        for (int b = 0; b < 2; ++b) {
+            const int n = wn + 16 * b + row;
+            bfr[b] = *(const bf16x8*)&Bs[n][kg ^ swz(n)];
+        }
 #pragma unroll
         for (int a = 0; a < 2; ++a)
 #pragma unroll
