@@ -208,6 +208,36 @@ __global__ void k_act_bwd(int64_t n, int c, const float* __restrict__ dA,
     dZb[e] = f2bf(g);
 }
 
+// The same dZ as bf16 only, with its column sums over rows
+// [b rows, (b + 1) rows) into part[b c + j] (block b), added in the order of
+// k_colsum_part, so the bias gradient needs no FP32 copy of dZ.
+__global__ __launch_bounds__(256) void k_act_bwd_colsum(int64_t n, int c, int64_t rows,
+                                                        const float* __restrict__ dA,
+                                                        const float* __restrict__ Zpre,
+                                                        uint16_t* __restrict__ dZb,
+                                                        float* __restrict__ part) {
+    __shared__ float red[256];
+    const int t = threadIdx.x, per = 256 / c;
+    const int64_t r0 = (int64_t)blockIdx.x * rows, r1 = min(n, r0 + rows);
+    float s = 0.f;
+    if (t < per * c) {
+        const int j = t % c;
+        for (int64_t i = r0 + t / c; i < r1; i += per) {
+            const int64_t e = i * c + j;
+            const float g = dA[e] * dsilu(Zpre[e]);
+            dZb[e] = f2bf(g);
+            s += g;
+        }
+    }
+    red[t] = s;
+    __syncthreads();
+    if (t < c) {
+        float a = 0.f;
+        for (int q = 0; q < per; ++q) a += red[q * c + t];
+        part[(int64_t)blockIdx.x * c + t] = a;
+    }
+}
+
 __global__ void k_f32_to_bf16(int64_t n, const float* __restrict__ x, uint16_t* __restrict__ y) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e < n) y[e] = f2bf(x[e]);
@@ -431,6 +461,15 @@ int gemm_tn_split(int M, int N, int64_t K, const uint16_t* A, int lda, const uin
     return check(hipGetLastError());
 }
 
+// Up to 4096 row ranges of n rows for column sums of c columns whose
+// partial sums fit in work_floats: B ranges of `rows` rows each.
+void row_ranges(int64_t n, int c, int64_t work_floats, int64_t& B, int64_t& rows) {
+    B = std::min<int64_t>(4096, (n + 1023) / 1024);
+    B = std::max<int64_t>(1, std::min<int64_t>(B, work_floats / c));
+    rows = (n + B - 1) / B;
+    B = (n + rows - 1) / rows;
+}
+
 // Column sums of dZ [n x c] into db over up to 4096 row ranges, whose
 // partial sums (in work) are added in range order.
 int colsum_split(int64_t n, int c, const float* dZ, float* db, float* work, int64_t work_floats,
@@ -439,10 +478,8 @@ int colsum_split(int64_t n, int c, const float* dZ, float* db, float* work, int6
         hipLaunchKernelGGL(k_colsum, dim3(c), dim3(256), 0, st, n, c, dZ, db);
         return check(hipGetLastError());
     }
-    int64_t B = std::min<int64_t>(4096, (n + 1023) / 1024);
-    B = std::max<int64_t>(1, std::min<int64_t>(B, work_floats / c));
-    const int64_t rows = (n + B - 1) / B;
-    B = (n + rows - 1) / rows;
+    int64_t B, rows;
+    row_ranges(n, c, work_floats, B, rows);
     hipLaunchKernelGGL(k_colsum_part, dim3((unsigned)B), dim3(256), 0, st, n, c, rows, dZ, work);
     hipLaunchKernelGGL(k_reduce_cols, dim3(c), dim3(256), 0, st, (int)B, c, work, db);
     return check(hipGetLastError());
@@ -526,24 +563,38 @@ int mlp_backward(const mlp_shape* s, const uint16_t* wb, int64_t n, const uint16
     int rc = 0;
     for (int l = L - 1; l >= 0; --l) {
         const int out = d.out[l], in = d.in[l];
+        // dZ_l as bf16 into work_b and db_l = column sums of dZ_l (partial
+        // sums in the dZf half of work_f)
         if (l == L - 1) {
-            rc = check(hipMemcpyAsync(dZf, dY, sizeof(float) * n * out, hipMemcpyDeviceToDevice, st));
-            if (rc) return rc;
-            hipLaunchKernelGGL(k_f32_to_bf16, dim3(nb(n * out, 256)), dim3(256), 0, st, n * out, dZf,
+            hipLaunchKernelGGL(k_f32_to_bf16, dim3(nb(n * out, 256)), dim3(256), 0, st, n * out, dY,
                                work_b);
+            rc = check(hipGetLastError());
+            if (rc) return rc;
+            rc = colsum_split(n, out, dY, grad + d.boff[l], dZf, n * wmax, st);
+            if (rc) return rc;
+        } else if (out <= 256) {
+            int64_t B, rows;
+            row_ranges(n, out, n * wmax, B, rows);
+            hipLaunchKernelGGL(k_act_bwd_colsum, dim3((unsigned)B), dim3(256), 0, st, n, out, rows,
+                               dA, Z + (int64_t)l * n * s->width, work_b, dZf);
+            hipLaunchKernelGGL(k_reduce_cols, dim3(out), dim3(256), 0, st, (int)B, out, dZf,
+                               grad + d.boff[l]);
+            rc = check(hipGetLastError());
+            if (rc) return rc;
         } else {
             hipLaunchKernelGGL(k_act_bwd, dim3(nb(n * out, 256)), dim3(256), 0, st, n, out, dA,
                                Z + (int64_t)l * n * s->width, dZf, work_b);
+            rc = check(hipGetLastError());
+            if (rc) return rc;
+            hipLaunchKernelGGL(k_colsum, dim3(out), dim3(256), 0, st, n, out, dZf, grad + d.boff[l]);
+            rc = check(hipGetLastError());
+            if (rc) return rc;
         }
-        rc = check(hipGetLastError());
-        if (rc) return rc;
         const uint16_t* prev = l == 0 ? X : A + (int64_t)(l - 1) * n * s->width;
-        // dW_l = dZ_l^T prev  (out x in), db_l = column sums of dZ_l.  dA_l is
-        // consumed (dZ_l is in dZf and work_b), so its n x wmax floats hold
-        // the partial sums until dA_{l-1} is formed below.
+        // dW_l = dZ_l^T prev  (out x in).  dA_l is consumed (dZ_l is in
+        // work_b), so its n x wmax floats hold the partial products until
+        // dA_{l-1} is formed below.
         rc = gemm_tn_split(out, in, n, work_b, out, prev, in, grad + d.woff[l], dA, n * wmax, st);
-        if (rc) return rc;
-        rc = colsum_split(n, out, dZf, grad + d.boff[l], dA, n * wmax, st);
         if (rc) return rc;
         // dA_{l-1} = dZ_l W_l  (n x in)
         if (l > 0) {
