@@ -280,15 +280,19 @@ def main():
         print(f"[bench] paper cylinder R=100: {row['elastic_s']:.3f} s per 1000 iterations",
               file=sys.stderr, flush=True)
         # the warm-start network on one sample per tree site: forward pass
-        # (bf16 MFMA; HBM-bound at 4,144 B per sample) and training step
+        # (bf16 MFMA; HBM-bound at 4,144 B per sample), inference (2,096 B per
+        # sample: no pre-activations kept) and training step
         from paper_2108_08783_amd import mlp
         nb = mlp.bench(7_484_227, reps=5)
         fwd_gbs = 4144 * nb["samples"] / (nb["forward"]["ms"] * 1e-3) / 1e9
+        inf_gbs = 2096 * nb["samples"] / (nb["infer"]["ms"] * 1e-3) / 1e9
         secondary["mlp_7M_samples"] = dict(
             nb, forward_achieved_gbs=round(fwd_gbs, 1),
-            forward_roofline_frac=round(fwd_gbs / PEAK_GBS, 4))
-        print(f"[bench] network: forward {nb['forward']['ms']:.2f} ms, training step "
-              f"{nb['train_step']['ms']:.2f} ms", file=sys.stderr, flush=True)
+            forward_roofline_frac=round(fwd_gbs / PEAK_GBS, 4),
+            infer_achieved_gbs=round(inf_gbs, 1), infer_roofline_frac=round(inf_gbs / PEAK_GBS, 4))
+        print(f"[bench] network: forward {nb['forward']['ms']:.2f} ms, inference "
+              f"{nb['infer']['ms']:.2f} ms, training step {nb['train_step']['ms']:.2f} ms",
+              file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu and args.workload == "tube":

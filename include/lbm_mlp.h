@@ -59,6 +59,13 @@ int mlp_gemm_bf16(int M, int N, int K, const uint16_t* A, int lda, int transA, c
 int mlp_forward(const mlp_shape* s, const float* params, const uint16_t* wb, int64_t n,
                 const uint16_t* X, float* Z, uint16_t* A, void* stream);
 
+/* Inference: as mlp_forward, but only the output Y (the last n * n_out
+ * block of Z) and the bf16 activations A are written; the hidden
+ * pre-activations are not kept, so no backward pass can follow.  Y is
+ * identical to mlp_forward's. */
+int mlp_infer(const mlp_shape* s, const float* params, const uint16_t* wb, int64_t n,
+              const uint16_t* X, float* Z, uint16_t* A, void* stream);
+
 /* Backward pass for the loss gradient dY (n x n_out FP32) of the forward
  * pass that produced Z and A: writes the gradient of every parameter into
  * grad (FP32, parameter layout).  Workspaces: work_f of

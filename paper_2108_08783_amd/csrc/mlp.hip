@@ -119,7 +119,8 @@ __device__ __forceinline__ void store_frag(uint16_t (&T)[64][LDK], const Frag& f
 
 // Epilogue (bias != null): C = acc + bias[n] and, when Aout != null,
 // Aout = bf16(silu(C)) at the same index (the fused bias and activation of a
-// forward layer).  One instantiation per operand layout, so each carries only
+// forward layer).  C == null (no accumulate, one slab): only Aout is
+// written, for inference without the pre-activations.  One instantiation per operand layout, so each carries only
 // the staging it uses.
 template <int transA, int transB, bool va, bool vb>
 __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const uint16_t* __restrict__ A,
@@ -138,7 +139,7 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const uint16_
     const int m0 = (int)(blockIdx.x / ntn) * TM, n0 = (int)(blockIdx.x % ntn) * TN;
     const int64_t kz = (int64_t)blockIdx.z * kchunk;
     const int kb = (int)kz, ke = (int)(kz + kchunk < K ? kz + kchunk : K);
-    C += (int64_t)blockIdx.z * M * ldc;
+    if (C) C += (int64_t)blockIdx.z * M * ldc;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
     f32x4 acc[2][2];
 #pragma unroll
@@ -187,11 +188,11 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const uint16_
             for (int r = 0; r < 4; ++r) {
                 const int gm = m0 + wm + 16 * a + rg + r, gn = n0 + wn + 16 * b + col;
                 if (gm < M && gn < N) {
-                    float* p = C + (int64_t)gm * ldc + gn;
-                    float v = accumulate ? *p + acc[a][b][r] : acc[a][b][r];
+                    const int64_t e = (int64_t)gm * ldc + gn;
+                    float v = accumulate ? C[e] + acc[a][b][r] : acc[a][b][r];
                     if (bias) v += bias[gn];
-                    *p = v;
-                    if (Aout) Aout[(int64_t)gm * ldc + gn] = f2bf(silu(v));
+                    if (C) C[e] = v;
+                    if (Aout) Aout[e] = f2bf(silu(v));
                 }
             }
 }
@@ -541,6 +542,30 @@ int mlp_forward(const mlp_shape* s, const float* params, const uint16_t* wb, int
         // Z_l = x W_l^T + b_l and A_l = bf16(silu(Z_l)) in the GEMM's epilogue
         launch_gemm<0, 1>(dim3(tiles((int)n, d.out[l])), st, (int)n, d.out[l], d.in[l], x, d.in[l],
                           wb + d.woff[l], d.in[l], Zl, d.out[l], 0, d.in[l], params + d.boff[l], Al);
+        const int rc = check(hipGetLastError());
+        if (rc) return rc;
+        x = Al;
+    }
+    return 0;
+}
+
+int mlp_infer(const mlp_shape* s, const float* params, const uint16_t* wb, int64_t n,
+              const uint16_t* X, float* Z, uint16_t* A, void* stream) {
+    if (!valid(s) || !params || !wb || !X || !Z || !A || n < 0)
+        return err("mlp_infer: bad arguments");
+    if (n == 0) return 0;
+    if (n > INT32_MAX || !tiles_fit(s, n)) return err("mlp_infer: too many samples per call");
+    const Dims d = dims(s);
+    hipStream_t st = (hipStream_t)stream;
+    const uint16_t* x = X;
+    for (int l = 0; l < d.L; ++l) {
+        const bool last = l == d.L - 1;
+        // hidden layers: A_l = bf16(silu(x W_l^T + b_l)) only; output layer:
+        // Y = x W^T + b into its block of Z
+        float* Yl = last ? Z + (int64_t)l * n * s->width : nullptr;
+        uint16_t* Al = last ? nullptr : A + (int64_t)l * n * s->width;
+        launch_gemm<0, 1>(dim3(tiles((int)n, d.out[l])), st, (int)n, d.out[l], d.in[l], x, d.in[l],
+                          wb + d.woff[l], d.in[l], Yl, d.out[l], 0, d.in[l], params + d.boff[l], Al);
         const int rc = check(hipGetLastError());
         if (rc) return rc;
         x = Al;

@@ -17,7 +17,7 @@ import numpy as np
 from . import lbm
 
 MLP_EXPORTS = ["mlp_param_count", "mlp_act_floats", "mlp_act_bf16", "mlp_gemm_bf16",
-               "mlp_forward", "mlp_backward", "mlp_mse", "mlp_mse_partials", "mlp_adam",
+               "mlp_forward", "mlp_infer", "mlp_backward", "mlp_mse", "mlp_mse_partials", "mlp_adam",
                "mlp_to_bf16", "mlp_last_error"]
 
 
@@ -39,6 +39,7 @@ def load():
         "mlp_param_count": ([P], L), "mlp_act_floats": ([P, L], L), "mlp_act_bf16": ([P, L], L),
         "mlp_gemm_bf16": ([I, I, I, P, I, I, P, I, I, P, I, I, P], I),
         "mlp_forward": ([P, P, P, L, P, P, P, P], I),
+        "mlp_infer": ([P, P, P, L, P, P, P, P], I),
         "mlp_backward": ([P, P, L, P, P, P, P, P, P, P, P], I),
         "mlp_mse": ([L, I, P, P, P, P, P, P, P], I), "mlp_mse_partials": ([L, I], L),
         "mlp_adam": ([L, P, P, P, P, P, F, F, F, F, L, P], I),
@@ -83,6 +84,11 @@ def mlp_to_bf16(x, y):
 
 def mlp_forward(shape, params, wb, n, X, Z, A):
     _check(load().mlp_forward(ctypes.byref(shape), _ptr(params), _ptr(wb), n, _ptr(X), _ptr(Z),
+                              _ptr(A), _stream()))
+
+
+def mlp_infer(shape, params, wb, n, X, Z, A):
+    _check(load().mlp_infer(ctypes.byref(shape), _ptr(params), _ptr(wb), n, _ptr(X), _ptr(Z),
                               _ptr(A), _stream()))
 
 
@@ -168,6 +174,15 @@ class Net:
         off = n * self.shape.depth * self.shape.width
         return self.Z[off:off + n * self.shape.n_out].view(n, self.shape.n_out)
 
+    def infer(self, Xb):
+        """Output only (no pre-activations kept for a backward pass); equal to
+        forward's.  Returns the FP32 view [n, n_out]."""
+        n = Xb.shape[0]
+        self._buffers(n)
+        mlp_infer(self.shape, self.params, self.wb, n, Xb, self.Z, self.A)
+        off = n * self.shape.depth * self.shape.width
+        return self.Z[off:off + n * self.shape.n_out].view(n, self.shape.n_out)
+
     def backward(self, Xb, dY):
         n = Xb.shape[0]
         mlp_backward(self.shape, self.wb, n, Xb, self.Z, self.A, dY, self.grad, self.work_f,
@@ -196,16 +211,16 @@ def flops_per_site(n_in=16, width=128, depth=4, n_out=4):
 
 
 def bench(n=7_484_227, reps=10, seed=0):
-    """Forward pass and training step of the default network on n samples
-    of random features, timed with HIP events on torch's current stream;
-    returns a dict of milliseconds and rates."""
+    """Forward pass, inference pass and training step of the default network
+    on n samples of random features, timed with HIP events on torch's
+    current stream; returns a dict of milliseconds and rates."""
     import torch
     net = Net(seed=seed)
     g = torch.Generator(device="cuda").manual_seed(seed)
     X = net.to_bf16(torch.randn(n, net.shape.n_in, device="cuda", generator=g))
     T = torch.randn(n, net.shape.n_out, device="cuda", generator=g)
     out = dict(samples=n, flop_per_sample=flops_per_site())
-    for name, fn in (("forward", lambda: net.forward(X)),
+    for name, fn in (("forward", lambda: net.forward(X)), ("infer", lambda: net.infer(X)),
                      ("train_step", lambda: net.train_step(X, T, lr=1e-4))):
         fn()
         torch.cuda.synchronize()
@@ -216,7 +231,7 @@ def bench(n=7_484_227, reps=10, seed=0):
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
-        flop = out["flop_per_sample"] * n * (1 if name == "forward" else 3)
+        flop = out["flop_per_sample"] * n * (3 if name == "train_step" else 1)
         out[name] = dict(ms=round(ms, 3), tflops=round(flop / (ms * 1e-3) / 1e12, 2))
         print(f"[mlp] {name}: {ms:.3f} ms for {n} samples, {flop / (ms * 1e-3) / 1e12:.1f} TFLOP/s",
               file=sys.stderr, flush=True)

@@ -64,6 +64,21 @@ def test_forward_matches_reference():
     assert _rel(Y, Yr) <= 1e-2
 
 
+def test_inference_equals_the_forward_output():
+    """The inference pass (no pre-activations stored) gives the forward
+    pass's output bit for bit, on 70,001 samples (many tiles and a ragged
+    last one), and stays within the forward bound of the reference."""
+    import torch
+    net, p, X, Xb, d = _net_and_ref(n=70001)
+    Yf = net.forward(Xb).clone()
+    net.Z.fill_(float("nan"))              # inference must write its whole output
+    Yi = net.infer(Xb)
+    torch.cuda.synchronize()
+    assert torch.equal(Yf, Yi)
+    Yr, _ = M.forward(p, X, d)
+    assert _rel(Yi.cpu().numpy(), Yr) <= 1e-2
+
+
 def test_backward_matches_reference():
     import torch
     net, p, X, Xb, d = _net_and_ref(n=257)
