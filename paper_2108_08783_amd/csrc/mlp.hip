@@ -117,6 +117,15 @@ __device__ __forceinline__ void store_frag(uint16_t (&T)[64][LDK], const Frag& f
     }
 }
 
+// Workgroups are handed to the 8 XCDs in turn, each XCD with its own L2:
+// block b of nblk takes id j per + min(j, rem) + k (j = b mod 8, k = b / 8),
+// so each XCD works through a contiguous range of ids (a bijection).
+__device__ __forceinline__ int xcd_order(int b, int nblk) {
+    const int per = nblk >> 3, rem = nblk & 7;
+    const int j = b & 7, k = b >> 3;
+    return j * per + (j < rem ? j : rem) + k;
+}
+
 // Epilogue (bias != null): C = acc + bias[n] and, when Aout != null,
 // Aout = bf16(silu(C)) at the same index (the fused bias and activation of a
 // forward layer).  C == null (no accumulate, one slab): only Aout is
@@ -133,13 +142,16 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const uint16_
     __shared__ __attribute__((aligned(16))) uint16_t Bs[TN][LDK];
     const int t = threadIdx.x;
     const int wave = t >> 6, lane = t & 63;
-    // tiles in order of n within m: the blocks that share a row strip of op(A)
-    // run together, so its second read comes from L2
-    const int ntn = (N + TN - 1) / TN;
-    const int m0 = (int)(blockIdx.x / ntn) * TM, n0 = (int)(blockIdx.x % ntn) * TN;
-    const int64_t kz = (int64_t)blockIdx.z * kchunk;
+    // (slab, tile) ids in XCD order, tiles in order of n within m: the tiles
+    // that share a row strip of op(A), and the tiles of one slab, run on one
+    // XCD close together, so a strip is read from HBM once
+    const int ntn = (N + TN - 1) / TN, nx = (int)gridDim.x;
+    const int id = xcd_order((int)blockIdx.x + nx * (int)blockIdx.z, nx * (int)gridDim.z);
+    const int tile = id % nx, zb = id / nx;
+    const int m0 = (tile / ntn) * TM, n0 = (tile % ntn) * TN;
+    const int64_t kz = (int64_t)zb * kchunk;
     const int kb = (int)kz, ke = (int)(kz + kchunk < K ? kz + kchunk : K);
-    if (C) C += (int64_t)blockIdx.z * M * ldc;
+    if (C) C += (int64_t)zb * M * ldc;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
     f32x4 acc[2][2];
 #pragma unroll
