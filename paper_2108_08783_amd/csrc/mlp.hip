@@ -40,7 +40,8 @@ __device__ __forceinline__ float dsilu(float z) {
 // quarter as 2 x 2 MFMA 16x16x32 tiles.  Split K: block z covers
 // k in [z kchunk, (z + 1) kchunk) and writes slab z of C (M ldc floats
 // each); with one slab this is the plain product.
-constexpr int TM = 64, TN = 64, TK = 32, LDK = TK + 8;
+constexpr int TM = 64, TN = 64, TK = 32, LDK = TK + 8, LDC = TN + 4;
+static_assert(2 * 64 * LDK * 2 <= TM * LDC * 4, "operand tiles fit in the output tile");
 
 // Staging of the 64 x 32 tile T[r][k] = src(r0 + r, k0 + k), with
 // src(r, k) = kmajor ? S[k ld + r] : S[r ld + k] and zeros outside r < R,
@@ -138,8 +139,13 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const uint16_
                                               int accumulate, int kchunk,
                                               const float* __restrict__ bias,
                                               uint16_t* __restrict__ Aout) {
-    __shared__ __attribute__((aligned(16))) uint16_t As[TM][LDK];
-    __shared__ __attribute__((aligned(16))) uint16_t Bs[TN][LDK];
+    // operand tiles during the K loop, then the output tile (row stride LDC
+    // floats) for the epilogue's row-wise stores
+    __shared__ __attribute__((aligned(16))) float smem[TM * LDC];
+    uint16_t (&As)[TM][LDK] = *reinterpret_cast<uint16_t (*)[TM][LDK]>(smem);
+    uint16_t (&Bs)[TN][LDK] = *reinterpret_cast<uint16_t (*)[TN][LDK]>(
+        reinterpret_cast<uint16_t*>(smem) + TM * LDK);
+    float (&Cs)[TM][LDC] = *reinterpret_cast<float (*)[TM][LDC]>(smem);
     const int t = threadIdx.x;
     const int wave = t >> 6, lane = t & 63;
     // (slab, tile) ids in XCD order, tiles in order of n within m: the tiles
@@ -190,23 +196,58 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const uint16_
                 acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bfr[b], acc[a][b], 0, 0, 0);
         __syncthreads();
     }
-    // lane holds rows 4*(lane/16) + r of column lane % 16 of each 16x16 tile
+    // lane holds rows 4*(lane/16) + r of column lane % 16 of each 16x16
+    // tile; the tile goes through LDS (the K loop ended with a barrier, so
+    // the operand tiles are dead) and leaves row by row: in each of 4 passes
+    // 16 consecutive threads write one whole row of the tile with 16-byte
+    // stores (4 columns each), so every store fills whole lines
     const int col = lane & 15, rg = (lane >> 4) * 4;
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int gm = m0 + wm + 16 * a + rg + r, gn = n0 + wn + 16 * b + col;
-                if (gm < M && gn < N) {
-                    const int64_t e = (int64_t)gm * ldc + gn;
-                    float v = accumulate ? C[e] + acc[a][b][r] : acc[a][b][r];
-                    if (bias) v += bias[gn];
-                    if (C) C[e] = v;
-                    if (Aout) Aout[e] = f2bf(silu(v));
-                }
+            for (int r = 0; r < 4; ++r) Cs[wm + 16 * a + rg + r][wn + 16 * b + col] = acc[a][b][r];
+    __syncthreads();
+    const bool vc = (!C || ((((uintptr_t)C & 15) == 0) && ((ldc & 3) == 0))) &&
+                    (!Aout || ((((uintptr_t)Aout & 7) == 0) && ((ldc & 3) == 0)));
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int row = (t >> 4) + 16 * j, c = (t & 15) * 4;
+        const int gm = m0 + row, gn = n0 + c;
+        if (gm >= M) break;
+        const float4 q = *(const float4*)&Cs[row][c];
+        float v[4] = {q.x, q.y, q.z, q.w};
+        const int64_t e = (int64_t)gm * ldc + gn;
+        if (vc && gn + 4 <= N) {
+            if (accumulate) {
+                const float4 o = *(const float4*)(C + e);
+                v[0] = o.x + v[0];
+                v[1] = o.y + v[1];
+                v[2] = o.z + v[2];
+                v[3] = o.w + v[3];
             }
+            if (bias) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) v[u] += bias[gn + u];
+            }
+            if (C) *(float4*)(C + e) = make_float4(v[0], v[1], v[2], v[3]);
+            if (Aout) {
+                const uint32_t lo = (uint32_t)f2bf(silu(v[0])) | ((uint32_t)f2bf(silu(v[1])) << 16);
+                const uint32_t hi = (uint32_t)f2bf(silu(v[2])) | ((uint32_t)f2bf(silu(v[3])) << 16);
+                *(uint2*)(Aout + e) = make_uint2(lo, hi);
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (gn + u >= N) break;
+                float x = accumulate ? C[e + u] + v[u] : v[u];
+                if (bias) x += bias[gn + u];
+                if (C) C[e + u] = x;
+                if (Aout) Aout[e + u] = f2bf(silu(x));
+            }
+        }
+    }
 }
 
 // dZ = dA * silu'(Zpre) (bf16 for the next GEMM, FP32 copy for the bias
