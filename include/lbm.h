@@ -33,11 +33,14 @@
  *     (+,+), (-,-), (+,-), (-,+).
  *   - Host arrays passed in are read during the call and never retained;
  *     host arrays passed out are written before the call returns.  All
- *     device memory is owned by the context and freed by lbm_destroy.
+ *     device memory is owned by the context and freed by lbm_destroy; it is
+ *     obtained from hipMalloc, or from the caller's allocator when one is
+ *     given to lbm_create_geometry_ex.
  *   - A context is thread-compatible, not thread-safe: one host thread at a
- *     time.  Work is enqueued on the context's own HIP stream
- *     (lbm_get_stream); lbm_step is asynchronous, the read calls
- *     synchronise.
+ *     time.  All work is enqueued on the context's HIP stream: the caller's
+ *     stream when one is given to lbm_create_geometry_ex, else a stream the
+ *     context creates (lbm_get_stream).  lbm_step is asynchronous, the read
+ *     calls synchronise that stream.
  */
 #ifndef LBM_H
 #define LBM_H
@@ -121,6 +124,31 @@ typedef struct {
     int64_t device_bytes;    /* device memory held by the context            */
 } lbm_info;
 
+/* Caller-supplied device resources (optional; see lbm_create_geometry_ex).
+ *   alloc(bytes, user) returns device memory of the current device, at least
+ *     `bytes` long and 256-byte aligned, or NULL on failure (reported as
+ *     LBM_ENOMEM); free(ptr, user) returns a block obtained from alloc.  Both
+ *     or neither must be set; with neither, hipMalloc / hipFree are used.
+ *     The context calls them from the creating call, from calls that need
+ *     read-out staging (first use, or a larger instance), from the first
+ *     lbm_cycle_delta of an instance and from lbm_destroy, always on the
+ *     calling thread.  Before it frees a block the context drains its
+ *     stream.
+ *   use_stream != 0: every operation of the context is enqueued on `stream`
+ *     (a hipStream_t; NULL means the null stream), which the context never
+ *     destroys and which must outlive it.  The step graphs are captured on
+ *     a private stream of the context and launched on `stream`.
+ *   user is passed through unchanged. */
+typedef void* (*lbm_alloc_fn)(size_t bytes, void* user);
+typedef void (*lbm_free_fn)(void* ptr, void* user);
+typedef struct {
+    lbm_alloc_fn alloc;
+    lbm_free_fn free;
+    void* user;
+    int32_t use_stream;
+    void* stream;
+} lbm_resources;
+
 /* ---- lifetime ----------------------------------------------------------- */
 
 /* Builds the site list, the neighbour (pull) table and the compacted
@@ -141,6 +169,17 @@ typedef struct {
 int lbm_create_geometry(lbm_ctx** out, const lbm_instance_desc* inst, int n_inst, int dtype,
                         double tau);
 
+/* lbm_create_geometry with the caller's device allocator and/or stream
+ * (res may be NULL: same as lbm_create_geometry).  Errors as
+ * lbm_create_geometry, and LBM_EINVAL if only one of alloc / free is set or
+ * the allocator returns a misaligned block. */
+int lbm_create_geometry_ex(lbm_ctx** out, const lbm_instance_desc* inst, int n_inst, int dtype,
+                           double tau, const lbm_resources* res);
+
+/* Whether ctx allocates through the caller's allocator (*allocator = 1) and
+ * enqueues on the caller's stream (*stream = 1); either pointer may be NULL. */
+int lbm_uses_caller_resources(const lbm_ctx* ctx, int* allocator, int* stream);
+
 /* Frees every resource of the context; NULL is accepted. */
 int lbm_destroy(lbm_ctx* ctx);
 
@@ -160,7 +199,7 @@ const char* lbm_last_error(const lbm_ctx* ctx);
 int lbm_set_wall_params(lbm_ctx* ctx, int inst, int mode, double F, double P0,
                         const double* k_per_segment, int n_seg);
 
-/* Local slip ratio (the closing discussion of Sec. 5: F need not be global;
+/* Local slip ratio (the closing discussion of Sec. 4: F need not be global;
  * the Sec. 2.3 relation ties it to the local Womersley number and
  * Delta r / R).  F_per_segment[s] in [0, 1) replaces, for wall segment s of
  * instance inst, the single F of the last lbm_set_wall_params call, which
@@ -237,7 +276,10 @@ int lbm_write_populations(lbm_ctx* ctx, int inst, const double* f);
  *   delta_u = max_x |u(x) - u_prev(x)|_inf / max_x |u(x)|_inf,
  *   delta_p = max_x |p(x) - p_prev(x)| / max_x |p(x) - P0|.
  * The first call after creation or lbm_init_fields returns +inf for both.
- * Synchronises. */
+ * The maxima are taken over the sites of the instance in FP32 (velocity
+ * and p - 1/3 from the FP32 moments of f(t); the snapshot is FP32).
+ * Synchronises.  Returns LBM_EDIVERGED if the velocity or pressure of any
+ * site is not finite (the snapshot is replaced all the same). */
 int lbm_cycle_delta(lbm_ctx* ctx, int inst, double* delta_u, double* delta_p);
 
 /* ---- introspection / tuning ---------------------------------------------- */

@@ -242,7 +242,7 @@ void orc_set_wall(void *h, int mode, double F, double P0, const double *k, int n
     }
 }
 
-/* Slip ratio F per wall segment (the closing discussion of Sec. 5: F may be
+/* Slip ratio F per wall segment (the closing discussion of Sec. 4: F may be
  * set locally, e.g. per vessel of a tree from the Sec. 2.3 relation between
  * F, the Womersley number and Delta r / R).  Replaces the single F of
  * orc_set_wall for segments 0 .. n_seg-1; returns -1 if n_seg differs from

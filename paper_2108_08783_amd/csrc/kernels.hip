@@ -774,7 +774,8 @@ __global__ __launch_bounds__(256) void k_read_pop(PopArgs a) {
 }
 
 // Cycle-to-cycle change of u and p against the stored snapshot; block
-// maxima are combined with unsigned atomics on the (non-negative) float bits.
+// maxima are combined with unsigned atomics on the (non-negative) float bits
+// (+inf, the largest of them, marks a non-finite site).
 template <int DT, typename I>
 __global__ __launch_bounds__(256) void k_delta(DeltaArgs a) {
     using acc = typename Codec<DT>::acc;
@@ -797,6 +798,14 @@ __global__ __launch_bounds__(256) void k_delta(DeltaArgs a) {
         }
         v[1] = fmaxf(fabsf(ux), fmaxf(fabsf(uy), fabsf(uz)));
         v[3] = fabsf((float)((double)dp + a.dp0));
+        // fmaxf drops NaN operands: a non-finite value at any site becomes
+        // +inf in all four maxima, which the host reports as divergence
+        const bool bad = !(fabsf(ux) <= 3.4e38f && fabsf(uy) <= 3.4e38f && fabsf(uz) <= 3.4e38f &&
+                           fabsf(dp) <= 3.4e38f);
+        if (bad) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) v[c] = __builtin_inff();
+        }
         sn[0] = ux;
         sn[1] = uy;
         sn[2] = uz;

@@ -112,9 +112,15 @@ struct lbm_ctx {
     bool tables_dirty = true, params_dirty = true;
     // launch configuration
     int block = 256, ibits = 32, use_graph = 1, xcd = 1, nt = 0, fused = 1, spt = 1;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;      // every operation of the context is enqueued here
+    bool own_stream = true;            // false: the caller's stream (not destroyed)
+    hipStream_t cap_stream = nullptr;  // private stream the step graphs are captured on
     hipGraphExec_t graph[2] = {nullptr, nullptr};  // by buffer parity at start
     int64_t device_bytes = 0;
+    // caller's device allocator (NULL: hipMalloc / hipFree)
+    lbm_alloc_fn alloc_fn = nullptr;
+    lbm_free_fn free_fn = nullptr;
+    void* alloc_user = nullptr;
 };
 
 namespace {
@@ -142,14 +148,33 @@ int fail(const lbm_ctx* c, int code, const char* fmt, ...) {
 int dalloc(lbm_ctx* c, void** p, size_t bytes) {
     *p = nullptr;
     if (bytes == 0) bytes = 256;
-    hipError_t e = hipMalloc(p, bytes);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(c, LBM_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    if (c->alloc_fn) {
+        *p = c->alloc_fn(bytes, c->alloc_user);
+        if (!*p) return fail(c, LBM_ENOMEM, "caller allocator returned NULL for %zu bytes", bytes);
+        if ((uintptr_t)*p % 256) {
+            c->free_fn(*p, c->alloc_user);
+            *p = nullptr;
+            return fail(c, LBM_EINVAL, "caller allocator returned a block not aligned to 256 bytes");
+        }
+    } else {
+        hipError_t e = hipMalloc(p, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(c, LBM_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+        }
     }
     c->owned.push_back({*p, bytes});
     c->device_bytes += (int64_t)bytes;
     return LBM_OK;
+}
+
+// Returns a block to whoever allocated it.  Blocks may still be in use by
+// work enqueued on the context's stream, so the stream is drained first.
+void release(lbm_ctx* c, void* p) {
+    if (c->free_fn)
+        c->free_fn(p, c->alloc_user);
+    else
+        (void)hipFree(p);
 }
 
 void dfree(lbm_ctx* c, void* p) {
@@ -160,7 +185,8 @@ void dfree(lbm_ctx* c, void* p) {
             c->owned.erase(c->owned.begin() + i);
             break;
         }
-    (void)hipFree(p);
+    if (c->stream || !c->own_stream) (void)hipStreamSynchronize(c->stream);
+    release(c, p);
 }
 
 // Device buffer released on every exit path of the scope that owns it.
@@ -355,12 +381,15 @@ int get_graph(lbm_ctx* c, int parity, hipGraphExec_t* out) {
         *out = c->graph[parity];
         return LBM_OK;
     }
+    // captured on a private stream (the caller's stream may be the null
+    // stream, which cannot be captured) and launched on the context's stream
+    if (!c->cap_stream) HIP_TRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     hipGraph_t g = nullptr;
-    HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    HIP_TRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
     hipError_t le = hipSuccess;
     for (int k = 0; k < GRAPH_STEPS && le == hipSuccess; ++k)
-        le = launch_step(c->dtype, c->ibits, step_args(c, (parity + k) & 1), c->block, c->stream);
-    hipError_t ce = hipStreamEndCapture(c->stream, &g);
+        le = launch_step(c->dtype, c->ibits, step_args(c, (parity + k) & 1), c->block, c->cap_stream);
+    hipError_t ce = hipStreamEndCapture(c->cap_stream, &g);
     if (le != hipSuccess || ce != hipSuccess) {
         if (g) (void)hipGraphDestroy(g);
         return fail(c, LBM_EDEVICE, "graph capture failed: %s",
@@ -627,7 +656,14 @@ int lbm_fast_axis(const lbm_instance_desc* inst, int n_inst, int* axis) {
 
 int lbm_create_geometry(lbm_ctx** out, const lbm_instance_desc* inst, int n_inst, int dtype,
                         double tau) {
+    return lbm_create_geometry_ex(out, inst, n_inst, dtype, tau, nullptr);
+}
+
+int lbm_create_geometry_ex(lbm_ctx** out, const lbm_instance_desc* inst, int n_inst, int dtype,
+                           double tau, const lbm_resources* res) {
     if (!out) return fail(nullptr, LBM_EINVAL, "out is NULL");
+    if (res && (!res->alloc) != (!res->free))
+        return fail(nullptr, LBM_EINVAL, "the allocator needs both alloc and free (or neither)");
     *out = nullptr;
     if (!(tau > 0.5)) return fail(nullptr, LBM_EINVAL, "tau must exceed 1/2 (got %g)", tau);
     if (elem_size(dtype) == 0) return fail(nullptr, LBM_EINVAL, "unknown dtype %d", dtype);
@@ -636,6 +672,15 @@ int lbm_create_geometry(lbm_ctx** out, const lbm_instance_desc* inst, int n_inst
     if (forced == -2) return fail(nullptr, LBM_EINVAL, "LBM_FAST_AXIS must be x, y, z or auto");
     lbm_ctx* c = new (std::nothrow) lbm_ctx();
     if (!c) return fail(nullptr, LBM_ENOMEM, "out of host memory");
+    if (res) {
+        c->alloc_fn = res->alloc;
+        c->free_fn = res->free;
+        c->alloc_user = res->user;
+        if (res->use_stream) {
+            c->stream = (hipStream_t)res->stream;
+            c->own_stream = false;
+        }
+    }
     // site order: instances whose fluid runs are longest along y or z are
     // stored with that axis exchanged for x
     std::vector<lbm_instance_desc> descs(inst, inst + n_inst);
@@ -684,10 +729,12 @@ int lbm_create_geometry(lbm_ctx** out, const lbm_instance_desc* inst, int n_inst
     }
     c->have16 = c->plan.max_abs_offset <= Sentinel<int16_t>::MAXABS - 1;
     c->ibits = 0;  // compressed addressing by default
-    hipError_t he = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
-    if (he != hipSuccess) {
-        delete c;
-        return fail(nullptr, LBM_EDEVICE, "hipStreamCreate failed: %s", hipGetErrorString(he));
+    if (c->own_stream) {
+        hipError_t he = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+        if (he != hipSuccess) {
+            delete c;
+            return fail(nullptr, LBM_EDEVICE, "hipStreamCreate failed: %s", hipGetErrorString(he));
+        }
     }
     int rc = 0;
     const size_t pop_bytes = (size_t)Q * c->np * c->esize;
@@ -773,11 +820,12 @@ int lbm_create_geometry(lbm_ctx** out, const lbm_instance_desc* inst, int n_inst
 
 int lbm_destroy(lbm_ctx* c) {
     if (!c) return LBM_OK;
-    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    if (c->stream || !c->own_stream) (void)hipStreamSynchronize(c->stream);
     drop_graphs(c);
-    for (auto& b : c->owned) (void)hipFree(b.p);
+    for (auto& b : c->owned) release(c, b.p);
     c->owned.clear();
-    if (c->stream) (void)hipStreamDestroy(c->stream);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     delete c;
     return LBM_OK;
 }
@@ -886,6 +934,13 @@ int lbm_step(lbm_ctx* c, int64_t n) {
     int rc = check_ready(c);
     if (rc) return rc;
     return run_steps(c, n);
+}
+
+int lbm_uses_caller_resources(const lbm_ctx* c, int* allocator, int* stream) {
+    if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
+    if (allocator) *allocator = c->alloc_fn != nullptr;
+    if (stream) *stream = !c->own_stream;
+    return LBM_OK;
 }
 
 int lbm_sync(lbm_ctx* c) {
@@ -1069,8 +1124,8 @@ int lbm_cycle_delta(lbm_ctx* c, int inst, double* delta_u, double* delta_p) {
     const double inf = std::numeric_limits<double>::infinity();
     if (delta_u) *delta_u = first ? inf : (v[1] > 0 ? v[0] / v[1] : (v[0] > 0 ? inf : 0.0));
     if (delta_p) *delta_p = first ? inf : (v[3] > 0 ? v[2] / v[3] : (v[2] > 0 ? inf : 0.0));
-    if (!std::isfinite(v[0]) || !std::isfinite(v[1]))
-        return fail(c, LBM_EDIVERGED, "non-finite velocity in instance %d", inst);
+    if (!std::isfinite(v[0]) || !std::isfinite(v[1]) || !std::isfinite(v[2]) || !std::isfinite(v[3]))
+        return fail(c, LBM_EDIVERGED, "non-finite velocity or pressure in instance %d", inst);
     return LBM_OK;
 }
 

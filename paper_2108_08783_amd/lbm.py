@@ -31,7 +31,8 @@ EXPORTS = [
     "lbm_get_stream", "lbm_time_steps", "lbm_read_fields", "lbm_read_populations",
     "lbm_write_populations", "lbm_cycle_delta", "lbm_get_info", "lbm_instance_sites",
     "lbm_set_launch", "lbm_autotune", "lbm_plan_export", "lbm_copy_probe",
-    "lbm_plan_compressed", "lbm_set_wall_F", "lbm_fast_axis",
+    "lbm_plan_compressed", "lbm_set_wall_F", "lbm_fast_axis", "lbm_create_geometry_ex",
+    "lbm_uses_caller_resources",
 ]
 
 
@@ -67,6 +68,46 @@ class Info(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class Resources(ctypes.Structure):
+    """lbm_resources: caller's device allocator and stream."""
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("user", ctypes.c_void_p),
+                ("use_stream", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+
+
+class TorchResources:
+    """torch's caching allocator and torch's current stream on the current
+    device, handed to lbm_create_geometry_ex: the library's device memory
+    then comes from torch's pool and its work is ordered with torch's work
+    on that stream.  Keep the object alive as long as the context."""
+
+    def __init__(self):
+        import torch
+        self.device = torch.cuda.current_device()
+        self.torch_stream = torch.cuda.current_stream(self.device)
+        alloc_impl = torch.cuda.caching_allocator_alloc
+        free_impl = torch.cuda.caching_allocator_delete
+        dev, stream = self.device, self.torch_stream
+
+        def alloc(nbytes, user):
+            try:
+                return alloc_impl(int(nbytes), dev, stream)
+            except Exception:   # out of memory: the library reports LBM_ENOMEM
+                return None
+
+        def free(ptr, user):
+            try:
+                free_impl(ptr)
+            except Exception:
+                pass
+
+        self._alloc, self._free = _ALLOC_FN(alloc), _FREE_FN(free)
+        self.struct = Resources(self._alloc, self._free, None, 1, self.torch_stream.cuda_stream)
+
+
 _lib = None
 
 
@@ -88,6 +129,8 @@ def load():
     P, I, D, L = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_int64
     sig = {
         "lbm_create_geometry": [P, P, I, I, D],
+        "lbm_create_geometry_ex": [P, P, I, I, D, P],
+        "lbm_uses_caller_resources": [P, P, P],
         "lbm_destroy": [P],
         "lbm_set_wall_params": [P, I, I, D, D, P, I],
         "lbm_set_wall_F": [P, I, P, I],
@@ -156,6 +199,25 @@ def lbm_create_geometry(geoms, dtype="f32", tau=0.8):
                                  float(tau))
     _check(rc, None)
     return out.value
+
+
+def lbm_create_geometry_ex(geoms, dtype="f32", tau=0.8, resources=None):
+    """As lbm_create_geometry with a Resources structure (or None)."""
+    lib = load()
+    arr, keep = _descs(geoms)
+    out = ctypes.c_void_p()
+    res = None if resources is None else ctypes.byref(resources)
+    rc = lib.lbm_create_geometry_ex(ctypes.byref(out), arr, len(geoms), DTYPES.get(dtype, dtype),
+                                    float(tau), res)
+    _check(rc, None)
+    return out.value
+
+
+def lbm_uses_caller_resources(ctx):
+    """(allocator, stream): whether ctx uses the caller's allocator / stream."""
+    a, st = ctypes.c_int(), ctypes.c_int()
+    _check(load().lbm_uses_caller_resources(ctx, ctypes.byref(a), ctypes.byref(st)), ctx)
+    return bool(a.value), bool(st.value)
 
 
 def lbm_destroy(ctx):
@@ -317,20 +379,34 @@ def lbm_fast_axis(geoms):
 
 # ------------------------------------------------------------------ wrapper --
 class Lattice:
-    """One library context holding one or more vessel instances."""
+    """One library context holding one or more vessel instances.
 
-    def __init__(self, geoms, dtype="f32", tau=0.8):
+    resources: "torch" (default) hands torch's caching allocator and torch's
+    current stream to the library (lbm_create_geometry_ex), so its device
+    memory comes from torch's pool and its work is ordered with torch's on
+    that stream; "library" lets the library call hipMalloc and create its
+    own stream (lbm_create_geometry)."""
+
+    def __init__(self, geoms, dtype="f32", tau=0.8, resources="torch"):
         if not isinstance(geoms, (list, tuple)):
             geoms = [geoms]
         self.geoms = list(geoms)
         self.tau = float(tau)
         self.dtype = dtype
-        self.ctx = lbm_create_geometry(self.geoms, dtype, tau)
+        if resources == "torch":
+            self._res = TorchResources()
+            self.ctx = lbm_create_geometry_ex(self.geoms, dtype, tau, self._res.struct)
+        elif resources == "library":
+            self._res = None
+            self.ctx = lbm_create_geometry(self.geoms, dtype, tau)
+        else:
+            raise ValueError(f"resources must be 'torch' or 'library', not {resources!r}")
 
     def close(self):
         if getattr(self, "ctx", None):
             lbm_destroy(self.ctx)
             self.ctx = None
+        self._res = None
 
     def __del__(self):
         try:

@@ -1,5 +1,5 @@
 """Local slip ratio F of the elastic wall rule (Sec. 2.3 and the closing
-discussion of Sec. 5).
+discussion of Sec. 4).
 
 The wall rule sets the wall-node velocity from U_R = F U_f, F being the
 ratio of the oscillating axial velocity at the extended wall (radius R) to

@@ -1,8 +1,8 @@
-"""Rigid against elastic wall shear stress, site by site (Sec. 4: the
+"""Rigid against elastic wall shear stress, site by site (Sec. 3, Fig. 11: the
 paper's pointwise comparison of instantaneous wall shear stress in its
 arterial geometry finds it generally higher with rigid walls), with the
 elastic wall applied both with one global F and with a local F per vessel
-from the Sec. 2.3 relation (the Sec. 5 discussion).
+from the Sec. 2.3 relation (the Sec. 4 discussion).
 
 Each workload runs three times from rest to a periodic state (cycle-to-cycle
 change of u and p below 1e-3): bounce-back walls, elastic walls with the

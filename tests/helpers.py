@@ -51,10 +51,11 @@ def configure(lat: lbm.Lattice, inst: int, p: Problem, init=True):
         lat.init_fields(inst, p.rho0, p.u0)
 
 
-def make_lattice(problems: List[Problem], dtype: str) -> lbm.Lattice:
+def make_lattice(problems: List[Problem], dtype: str, resources: str = "torch") -> lbm.Lattice:
     taus = {p.tau for p in problems}
     assert len(taus) == 1
-    lat = lbm.Lattice([p.geo for p in problems], dtype=dtype, tau=problems[0].tau)
+    lat = lbm.Lattice([p.geo for p in problems], dtype=dtype, tau=problems[0].tau,
+                      resources=resources)
     # all wall modes first (a mode change rebuilds the tables once), then
     # the initial states
     for k, p in enumerate(problems):

@@ -4,7 +4,8 @@ Adam) against the FP64 NumPy reference on identical bf16-rounded inputs.
 Tolerances: the GEMM accumulates in FP32, so it matches FP64 on the same
 bf16 operands to ~1e-6 relative.  Forward and backward round activations
 and back-propagated gradients to bf16 between layers (2^-9 relative per
-rounding), so whole tensors are held to 1e-2 relative (max-norm)."""
+rounding), so whole tensors are held to 1e-2 relative (max-norm) and the
+FP32-accumulated loss to 1e-3."""
 import numpy as np
 import pytest
 
@@ -54,7 +55,9 @@ def _net_and_ref(n=300, dims=(16, 128, 4, 4), seed=3):
 
 
 def _rel(a, b):
-    return np.abs(a - b).max() / np.abs(b).max()
+    r = np.abs(a - b).max() / np.abs(b).max()
+    print(f"MLP rel err {r:.3e}", flush=True)
+    return r
 
 
 def test_forward_matches_reference():
@@ -91,7 +94,7 @@ def test_backward_matches_reference():
     off = 0
     for i, o in d:          # per tensor: W then b
         for size in (i * o, o):
-            assert _rel(g[off:off + size], gr[off:off + size]) <= 2e-2, (i, o, size)
+            assert _rel(g[off:off + size], gr[off:off + size]) <= 1e-2, (i, o, size)
             off += size
 
 
@@ -113,7 +116,7 @@ def test_backward_with_split_sums_matches_reference_and_is_deterministic():
     off = 0
     for i, o in d:          # per tensor: W then b
         for size in (i * o, o):
-            assert _rel(g1[off:off + size], gr[off:off + size]) <= 2e-2, (i, o, size)
+            assert _rel(g1[off:off + size], gr[off:off + size]) <= 1e-2, (i, o, size)
             off += size
 
 
@@ -127,7 +130,8 @@ def test_loss_and_adam_match_reference():
     loss = net.train_step(Xb, _t(T, torch.float32), _t(w, torch.float32), lr=1e-3)
     Yr, cache = M.forward(p, X, d)
     Lr, dYr = M.mse(Yr, T, w)
-    assert loss.item() == pytest.approx(Lr, rel=1e-2)
+    print(f"MLP loss rel err {abs(loss.item() - Lr) / Lr:.3e}", flush=True)
+    assert loss.item() == pytest.approx(Lr, rel=1e-3)
     gr = M.backward(p, cache, dYr, d)
     pr, _, _ = M.adam(p, gr, np.zeros_like(p), np.zeros_like(p), 1, lr=1e-3)
     step_gpu = net.state() - p

@@ -58,7 +58,7 @@ def test_small_tube_density_driven(dtype, mode):
     e = H.errors(g, r, P0=p.P0)
     record(f"tube8_{'elastic' if mode else 'bb'}", e, dtype=dtype, steps=1000)
     assert e["u"] <= TOL[dtype] and e["p"] <= TOL[dtype]
-    assert e["wss"] <= 10 * TOL[dtype]
+    assert e["wss"] <= TOL[dtype]
     if mode == lbm.ELASTIC:
         assert e["dr"] <= 1e-6
 
@@ -76,7 +76,7 @@ def test_pulsatile_elastic_tube(dtype, fused):
     record("tube12_pulsatile_elastic", e, dtype=dtype, steps=1000, fused=fused)
     if dtype in TOL:
         assert e["u"] <= TOL[dtype] and e["p"] <= TOL[dtype]
-        assert e["wss"] <= 10 * TOL[dtype]
+        assert e["wss"] <= TOL[dtype]
     else:
         bound = {"f16": 1e-2, "bf16": 5e-2}[dtype]
         assert e["u"] <= bound and e["p"] <= bound
@@ -95,7 +95,7 @@ def test_random_boxes_every_link_type(dtype, seed, fused, addr):
     e = H.errors(g, r, P0=p.P0)
     record(f"random_box_{seed}", e, dtype=dtype, steps=60, fused=fused, addr=addr)
     tol = TOL[dtype]
-    assert e["u"] <= 10 * tol and e["p"] <= tol and e["wss"] <= 100 * tol
+    assert e["u"] <= tol and e["p"] <= tol and e["wss"] <= tol
 
 
 @pytest.mark.parametrize("dtype", ["f16", "bf16"])
@@ -135,7 +135,7 @@ def test_many_random_boxes_in_one_context(dtype):
         o.step(80)
         e = H.errors(lat.read_fields(k), o.read(), P0=p.P0)
         record(f"many_boxes_inst{k}", e, dtype=dtype, steps=80, mode=p.mode)
-        assert e["u"] <= 10 * TOL[dtype] and e["p"] <= TOL[dtype]
+        assert e["u"] <= TOL[dtype] and e["p"] <= TOL[dtype]
     lat.close()
 
 
@@ -156,7 +156,7 @@ def test_batch_of_uneven_instances(dtype):
         o.step(300)
         e = H.errors(lat.read_fields(k), o.read(), P0=p.P0)
         record(f"batch_inst{k}", e, dtype=dtype, steps=300)
-        assert e["u"] <= 10 * TOL[dtype] and e["p"] <= TOL[dtype]
+        assert e["u"] <= TOL[dtype] and e["p"] <= TOL[dtype]
     lat.close()
 
 
@@ -243,18 +243,54 @@ def test_divergence_is_reported():
     lat.close()
 
 
-def test_cycle_delta_monitor():
-    p = H.tube_problem(6, 24, seed=9)
+def _host_delta(prev, cur, P0):
+    """Cycle-to-cycle change from two (rho, u) snapshots, as the monitor
+    defines it: max|du|_inf / max|u|_inf and max|dp| / max|p - P0|."""
+    (r1, u1), (r2, u2) = prev, cur
+    du = np.abs(u2 - u1).max() / np.abs(u2).max()
+    dp = np.abs(r2 / 3 - r1 / 3).max() / np.abs(r2 / 3 - P0).max()
+    return du, dp
+
+
+def test_cycle_delta_monitor_against_snapshots_and_oracle():
+    """The periodicity monitor (lbm_cycle_delta, device max-reduction over
+    FP32 snapshots) against the same quantity differenced on the host from
+    two lbm_read_fields snapshots (FP32 rounding), and against the FP64
+    oracle's snapshots, early in the transient (changes of order 0.1) and
+    after seven cycles (order 1e-3, the convergence threshold); the first
+    call returns inf and an unchanged state returns 0."""
+    p = H.tube_problem(6, 24, seed=9, period=200.0)
     lat = H.make_lattice([p], "f32")
+    o = H.make_oracle(p)
+
+    def snap():
+        r, u, _, _ = lat.read_fields(0, wss=False, wall_dr=False)
+        ro, uo, _, _ = o.read()
+        return (r, u), (ro, uo)
+
     lat.step(50)
+    o.step(50)
     du, dp = lat.cycle_delta(0)
     assert np.isinf(du) and np.isinf(dp)
+    g_prev, o_prev = snap()
     du, dp = lat.cycle_delta(0)
     assert du == 0.0 and dp == 0.0
-    lat.step(40)
-    du, dp = lat.cycle_delta(0)
-    rho1, u1, _, _ = lat.read_fields(0)
-    assert 0 < du < np.inf and 0 < dp < np.inf
+    for cycles, lo in ((1, 0.05), (6, 2e-4)):
+        for c in range(cycles):
+            lat.step(200)
+            o.step(200)
+            du, dp = lat.cycle_delta(0)
+            g_cur, o_cur = snap()
+            if c < cycles - 1:   # the monitor's snapshot is the last call's
+                g_prev, o_prev = g_cur, o_cur
+        du_h, dp_h = _host_delta(g_prev, g_cur, p.P0)
+        du_o, dp_o = _host_delta(o_prev, o_cur, p.P0)
+        record("cycle_delta", dict(du=du, dp=dp, du_host=du_h, dp_host=dp_h, du_oracle=du_o,
+                                   dp_oracle=dp_o), dtype="f32", cycles=cycles)
+        assert du > lo and dp > lo / 4
+        assert du == pytest.approx(du_h, rel=1e-5) and dp == pytest.approx(dp_h, rel=1e-4)
+        assert abs(du - du_o) <= 2e-5 and abs(dp - dp_o) <= 2e-5
+        g_prev, o_prev = g_cur, o_cur
     lat.close()
 
 
@@ -344,18 +380,28 @@ def _from_workload(wl, k, rng):
                      u0=2e-3 * rng.uniform(-1, 1, (n, 3)))
 
 
+def _oracle_steps(o, steps, label, chunk=250):
+    """Advances the oracle in chunks, printing progress (long CPU runs)."""
+    done = 0
+    while done < steps:
+        n = min(chunk, steps - done)
+        o.step(n)
+        done += n
+        print(f"[oracle] {label}: {done}/{steps} steps", flush=True)
+
+
 def test_full_size_tree_parity():
     """The 7,484,227-site Murray tree of the benchmark (79 stiffness
     segments, 48 outlets), in the benchmark's launch configuration
-    (autotuned), 100 steps against the oracle over every site: FP64 storage
-    to rounding, FP32 within 1e-5 on u and p; FP16 and BF16 storage stated
-    (bounded loosely)."""
+    (autotuned), 1000 steps from a perturbed state against the oracle over
+    every site: FP64 storage to rounding, FP32 within 1e-5 on u and p; FP16
+    and BF16 storage stated (bounded loosely)."""
     from paper_2108_08783_amd import workloads
     wl = workloads.tree()
     p = _from_workload(wl, 0, np.random.default_rng(31))
-    steps = 100
+    steps = 1000
     o = H.make_oracle(p)
-    o.step(steps)
+    _oracle_steps(o, steps, "tree")
     ref = o.read()
     del o
     for dtype, bound in (("f64", 1e-11), ("f32", 1e-5), ("f16", 5e-3), ("bf16", 5e-2)):
@@ -365,23 +411,25 @@ def test_full_size_tree_parity():
         e = H.errors(lat.read_fields(0), ref, P0=p.P0)
         record("tree_full_size", e, dtype=dtype, steps=steps, launch=lat.info())
         assert e["u"] <= bound and e["p"] <= bound, dtype
+        if dtype in TOL:   # wall shear stress: stated, held to 10x the bound
+            assert e["wss"] <= 10 * bound, dtype
         lat.close()
 
 
 def test_full_size_sweep_parity_sampled():
     """The 64-instance sweep of the benchmark (19.7M sites, one batched
-    launch per step, autotuned), 100 steps; six instances drawn with a fixed
-    seed are compared with the oracle over every one of their sites."""
+    launch per step, autotuned), 1000 steps; six instances drawn with a
+    fixed seed are compared with the oracle over every one of their sites."""
     from paper_2108_08783_amd import workloads
     wl = workloads.sweep()
     rng = np.random.default_rng(47)
     probs = [_from_workload(wl, k, rng) for k in range(len(wl.geoms))]
     pick = sorted(rng.choice(len(probs), 6, replace=False).tolist())
-    steps = 100
+    steps = 1000
     refs = {}
     for k in pick:
         o = H.make_oracle(probs[k])
-        o.step(steps)
+        _oracle_steps(o, steps, f"sweep instance {k}", chunk=500)
         refs[k] = o.read()
     for dtype, bound in (("f32", 1e-5), ("f16", 5e-3)):
         lat = H.make_lattice(probs, dtype)
@@ -391,6 +439,8 @@ def test_full_size_sweep_parity_sampled():
             e = H.errors(lat.read_fields(k), refs[k], P0=probs[k].P0)
             record(f"sweep64_inst{k}", e, dtype=dtype, steps=steps)
             assert e["u"] <= bound and e["p"] <= bound, (dtype, k)
+            if dtype == "f32":   # wall shear stress: stated, held to 10x the bound
+                assert e["wss"] <= 10 * bound, k
         lat.close()
 
 
@@ -429,7 +479,7 @@ def test_population_buffers_beyond_2GiB(dtype, launch):
         record(f"beyond_2GiB_box{k}", e, dtype=dtype, steps=steps, launch=launch)
         if dtype in TOL:
             tol = TOL[dtype]
-            assert e["u"] <= 10 * tol and e["p"] <= tol and e["wss"] <= 100 * tol, k
+            assert e["u"] <= tol and e["p"] <= tol and e["wss"] <= tol, k
         else:
             bound = {"f16": 1e-2, "bf16": 5e-2}[dtype]
             assert e["u"] <= bound and e["p"] <= bound, k
@@ -485,7 +535,7 @@ def test_invalid_arguments_are_rejected_and_leave_the_context_usable():
     o.step(60)
     e = H.errors(lat.read_fields(0), o.read(), P0=p.P0)
     record("random_box_5_after_rejected_calls", e, dtype="f32", steps=60)
-    assert e["u"] <= 10 * TOL["f32"] and e["p"] <= TOL["f32"]
+    assert e["u"] <= TOL["f32"] and e["p"] <= TOL["f32"]
     lat.close()
 
 
@@ -514,7 +564,7 @@ def test_wall_changes_mid_run(dtype):
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_slip_ratio_per_segment(dtype):
-    """A local F (Sec. 5 discussion): the three wall segments of a random
+    """A local F (Sec. 4 discussion): the three wall segments of a random
     box get F = 0.1, 0.5 and 0.9, then new values mid-run, on both sides."""
     p = H.random_box_problem(1)
     p.F_seg = [0.1, 0.5, 0.9]
@@ -527,7 +577,7 @@ def test_slip_ratio_per_segment(dtype):
         o.step(steps)
         e = H.errors(lat.read_fields(0), o.read(), P0=p.P0)
         record(f"slip_per_segment_{F_seg}", e, dtype=dtype, steps=steps)
-        assert e["u"] <= 10 * TOL[dtype] and e["p"] <= TOL[dtype]
+        assert e["u"] <= TOL[dtype] and e["p"] <= TOL[dtype]
     with pytest.raises(lbm.LbmError):
         lat.set_wall_F(0, [0.5, 0.5, 1.0])
     with pytest.raises(lbm.LbmError):
@@ -562,7 +612,7 @@ def test_random_boxes_with_exchanged_fast_axis(axis, fused, monkeypatch):
         g, r = run_pair(p, "f64", 60, launch=dict(boundary_fused=fused))
         e = H.errors(g, r, P0=p.P0)
         record(f"random_box_{seed}_axis_{axis}", e, dtype="f64", steps=60, fused=fused)
-        assert e["u"] <= 10 * TOL["f64"] and e["p"] <= TOL["f64"] and e["wss"] <= 100 * TOL["f64"]
+        assert e["u"] <= TOL["f64"] and e["p"] <= TOL["f64"] and e["wss"] <= TOL["f64"]
 
 
 def test_populations_of_an_exchanged_instance(monkeypatch):
@@ -612,3 +662,46 @@ def test_device_initialisation_of_an_exchanged_instance(monkeypatch):
     assert np.abs(ga[1] - u).max() <= 1e-6 and np.abs(gb[1] - u).max() <= 1e-6
     a.close()
     b.close()
+
+
+def test_torch_memory_and_stream():
+    """The context takes its device memory from torch's caching allocator
+    and enqueues on torch's current stream (here a side stream of default
+    priority): torch's allocated bytes grow by the context's device bytes
+    and return after lbm_destroy; a device initial state written by torch
+    on that stream is consumed by the library without a host
+    synchronisation; the run matches the oracle, and bit for bit the same
+    run with library-owned memory and stream."""
+    import torch
+    p = H.random_box_problem(3)
+    n = p.geo.n_fluid
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        before = torch.cuda.memory_allocated()
+        lat = H.make_lattice([p], "f32")
+        assert lbm.lbm_uses_caller_resources(lat.ctx) == (True, True)
+        assert lat.stream == side.cuda_stream
+        grown = torch.cuda.memory_allocated() - before
+        assert grown >= lat.info()["device_bytes"] > 0
+        ru = torch.empty((n, 4), dtype=torch.float32, device="cuda")
+        ru[:, 0] = torch.tensor(p.rho0, device="cuda")
+        ru[:, 1:] = torch.tensor(p.u0, device="cuda")
+        lat.init_fields_device(0, ru)      # ordered after torch's writes on `side`
+        lat.step(60)
+        g = lat.read_fields(0)
+        lat.close()
+        torch.cuda.synchronize()
+        assert torch.cuda.memory_allocated() - before <= 4 * n * 4 + 4096
+    o = H.make_oracle(p)
+    o.step(60)
+    e = H.errors(g, o.read(), P0=p.P0)
+    record("random_box_3_torch_stream", e, dtype="f32", steps=60)
+    assert e["u"] <= TOL["f32"] and e["p"] <= TOL["f32"] and e["wss"] <= TOL["f32"]
+    ref = H.make_lattice([p], "f32", resources="library")
+    assert lbm.lbm_uses_caller_resources(ref.ctx) == (False, False)
+    ref.init_fields(0, np.asarray(ru[:, 0].cpu(), np.float64), np.asarray(ru[:, 1:].cpu(), np.float64))
+    ref.step(60)
+    gr = ref.read_fields(0)
+    ref.close()
+    for a, b in zip(g, gr):
+        assert np.array_equal(a, b)

@@ -2,7 +2,7 @@
 0.94M sites, drive period 4000 steps): run to a periodic state with each wall
 rule, the elastic walls (one global F, and one F per vessel from the
 Sec. 2.3 relation) must give a lower wall shear stress than bounce-back at
-nearly every wall site, as in the paper's pointwise comparison (Sec. 4)."""
+nearly every wall site, as in the paper's pointwise comparison (Sec. 3, Fig. 11)."""
 import pytest
 
 pytestmark = pytest.mark.gpu

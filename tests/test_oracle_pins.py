@@ -311,7 +311,7 @@ def _two_slip_channel(H, F_lo, F_hi, tau=0.8):
 
 
 def test_elastic_wall_slip_ratio_per_segment():
-    """P5 with a local F (closing discussion of Sec. 5): the two halves of a
+    """P5 with a local F (closing discussion of Sec. 4): the two halves of a
     wide duct have F = 0.1 and 0.7.  The steady mid-section approaches the
     lopsided parabola through the two slip conditions (error shrinking
     about 2.5x per doubling, as for one F), while its mirror image stays
@@ -459,3 +459,141 @@ def test_womersley_rigid_pipe():
     err = np.abs(uh - ua) / np.abs(ua).max()
     assert err.max() <= 0.05
     assert np.sqrt((err ** 2).mean()) <= 0.02
+
+
+# --------------------------------------- finite stiffness (P5, Sec. 2.4) --
+def test_elastic_wall_finite_stiffness_follows_local_pressure():
+    """P5 at finite stiffness: in a pressure-driven channel whose wall is soft
+    enough that the extension Delta E = (p - P0)/k runs from about 3 at the
+    inlet to 0 at the outlet, each section is locally a slip-Poiseuille
+    parabola whose slip ratio s = (F + Delta E)/(1 + Delta E) comes from that
+    section's own wall-node pressure (Sec. 2.3 U_w with Delta r = 1 + Delta E,
+    Sec. 2.4 extension law; lubrication, since s varies slowly along the
+    channel).  The profile shape (normalised by its own amplitude) must
+    match the local-s parabola to 1 % at three sections, and miss the s = F
+    parabola (Delta E dropped) by several per cent."""
+    H, W, L, F, k = 4, 16, 64, 0.5, 2e-5
+    P0 = 0.9999 / 3
+    g = inputs.duct(W, H, L)
+    o = oracle.Oracle(g.labels, 0.8)
+    o.set_wall(1, F=F, P0=P0, k=[k])
+    o.set_iolet(0, 0, 1.0001)
+    o.set_iolet(1, 0, 0.9999)
+    o.init_fields()
+    nu = 0.1
+    o.step(int(3.0 * 14 * H * H / (math.pi ** 2 * nu) / (1 - 0.9)))
+    rho, u, _, dr = o.read()
+    xyz = o.coords()
+    Yw = (H + 1) / 2
+    for zc in (L // 4, L // 2, 3 * L // 4):
+        sel = (xyz[:, 2] == zc) & (xyz[:, 0] == W // 2)
+        y = xyz[sel, 1] - (H + 1) / 2
+        uz = u[sel, 2]
+        edge = np.abs(y) == y.max()
+        dE = max(0.0, (rho[sel][edge].mean() / 3 - P0) / k)
+        s = (F + dE) / (1 + dE)
+        assert dE > 1.0
+        # the oracle's own wall distance at those sites is 1 + Delta E
+        assert dr[sel][edge] == pytest.approx(1 + dE, rel=1e-6)
+
+        def shape_err(b2):
+            shape = b2 - y ** 2
+            amp = (uz @ shape) / (shape @ shape)
+            return np.abs(uz - amp * shape).max() / uz.max()
+
+        assert shape_err(cf.slip_half_width_sq(Yw, s)) <= 0.01, zc
+        assert shape_err(cf.slip_half_width_sq(Yw, F)) >= 0.04, zc
+
+
+# ------------------------------------------- velocity inlet (Sec. 3) --------
+@pytest.mark.parametrize("tau", [TAU_MAGIC, 0.8])
+def test_velocity_inlet_imposes_its_flux(tau):
+    """Velocity inlet (Sec. 3, reading R6): a duct whose inlet prescribes the
+    plane-Poiseuille profile 1.5 u (1 - (y/h)^2) (weights per fluid site next
+    to the inlet, uniform across the span) against a fixed-density outlet.
+    At the steady state every cross-section carries the prescribed mass flux
+    sum(rho w u) of the inlet sites to 1e-3, and (at the halfway-wall tau,
+    where bounce-back is exact) the developed mid-section is the parabola of
+    half-width H/2 to 1e-3."""
+    H, W, L, ubar = 8, 32, 32, 0.01
+    g = inputs.duct(W, H, L)
+    yy = np.arange(H + 2) - (H + 1) / 2
+    prof = 1.5 * (1 - (yy / (H / 2)) ** 2)
+    w = np.broadcast_to(prof[None, :, None], g.labels.shape).astype(np.float32)
+    o = oracle.Oracle(g.labels, tau, iolet_weight=w)
+    o.set_wall(0)
+    o.set_iolet(0, 1, ubar, 0.0, 1.0, 0.0, (0, 0, 1))
+    o.set_iolet(1, 0, 1.0)
+    o.init_fields()
+    nu = (tau - 0.5) / 3
+    o.step(int(3.0 * (14 * H * H / (math.pi ** 2 * nu) + 2 * L * math.sqrt(3))))
+    rho, u, _, _ = o.read()
+    xyz = o.coords()
+    first = xyz[:, 2] == 1
+    wsite = w[xyz[:, 2], xyz[:, 1], xyz[:, 0]]
+    q_in = (rho[first] * wsite[first] * ubar).sum()
+    for z in range(1, L + 1):
+        plane = xyz[:, 2] == z
+        assert (rho[plane] * u[plane, 2]).sum() == pytest.approx(q_in, rel=1e-3), z
+    if tau == TAU_MAGIC:
+        sel = (xyz[:, 2] == L // 2) & (xyz[:, 0] == W // 2)
+        y = xyz[sel, 1] - (H + 1) / 2
+        shape = (H / 2) ** 2 - y ** 2
+        amp = (u[sel, 2] @ shape) / (shape @ shape)
+        assert np.abs(u[sel, 2] - amp * shape).max() / u[sel, 2].max() <= 1e-3
+
+
+# ------------------------------------ wall shear stress, given normals ------
+def test_wall_shear_stress_with_supplied_normals():
+    """Reading R8 with the caller's normals: in the halfway-wall channel the
+    deviatoric stress at the wall-adjacent node is a pure yz shear sigma of
+    magnitude G |y| (steady momentum balance).  For a unit normal n turned by
+    theta about the flow axis, t = sigma n is tangential and WSS = G|y| cos
+    theta; turned by theta about the spanwise axis, the tangential part of t
+    is G|y| |cos 2 theta|.  The populations of one run are read back under
+    three sets of normals."""
+    H = 8
+    W, L = 8 * H, 4 * H
+    g = inputs.duct(W, H, L)
+    base = oracle.Oracle(g.labels, TAU_MAGIC)
+    base.set_wall(0)
+    base.set_iolet(0, 0, 1.0001)
+    base.set_iolet(1, 0, 0.9999)
+    base.init_fields()
+    nu = (TAU_MAGIC - 0.5) / 3
+    base.step(int(3.0 * 14 * H * H / (math.pi ** 2 * nu)))
+    f = base.populations()
+    rho, _, w_fallback, _ = base.read()
+    xyz = base.coords()
+    zc = L // 2
+
+    def mean_rho(z):
+        return rho[xyz[:, 2] == z].mean()
+
+    G = -(mean_rho(zc + 1) - mean_rho(zc - 1)) / 2 / 3
+    sel = (xyz[:, 2] == zc) & (xyz[:, 0] == W // 2)
+    y = xyz[sel, 1] - (H + 1) / 2
+    edge = np.abs(y) == y.max()
+    assert w_fallback[sel][edge] == pytest.approx(G * y.max(), rel=2e-3)
+    theta = math.radians(35.0)
+    sign = np.sign(np.arange(H + 2) - (H + 1) / 2)[None, :, None]   # outward in y
+    cases = {
+        "about z": (np.sin(theta) * np.ones_like(sign), np.cos(theta) * sign, 0 * sign,
+                    math.cos(theta)),
+        "about x": (0 * sign, np.cos(theta) * sign, np.sin(theta) * np.ones_like(sign),
+                    abs(math.cos(2 * theta))),
+    }
+    for name, (nx_, ny_, nz_, factor) in cases.items():
+        nrm = np.zeros(g.labels.shape + (3,), np.float32)
+        nrm[..., 0] = nx_
+        nrm[..., 1] = ny_
+        nrm[..., 2] = nz_
+        o = oracle.Oracle(g.labels, TAU_MAGIC, normal=nrm)
+        o.set_wall(0)
+        o.set_iolet(0, 0, 1.0001)
+        o.set_iolet(1, 0, 0.9999)
+        o.set_populations(f)
+        _, _, wss, _ = o.read()
+        got = wss[sel][edge]
+        assert got == pytest.approx(G * y.max() * factor, rel=3e-3), name
+        assert np.all(wss[sel][~edge] == 0.0)

@@ -1,5 +1,5 @@
 """The local slip ratio F (Sec. 2.3 relation, applied per segment as the
-Sec. 5 discussion proposes), pinned without Bessel functions: the profile
+Sec. 4 discussion proposes), pinned without Bessel functions: the profile
 1 - M J0(Lambda r/R)/J0(Lambda) is the solution of the oscillating
 momentum equation that is regular on the axis and moves with the wall, so a
 finite-difference solve of that equation must give the same ratio.  No
