@@ -263,6 +263,30 @@ int lbm_time_steps(lbm_ctx* ctx, int64_t n, double* ms);
 int lbm_read_fields(lbm_ctx* ctx, int inst, double* rho, double* u, double* wss,
                     float* wall_dr);
 
+/* Size of the per-device staging array of lbm_read_fields_noalloc, and the
+ * largest instance (in sites) it can read: 44 bytes per site (rho, u, wss
+ * as doubles, wall_dr as float) after a 256-byte flag block. */
+#define LBM_NOALLOC_SCRATCH_BYTES (96u << 20)
+#define LBM_NOALLOC_MAX_SITES (((int64_t)LBM_NOALLOC_SCRATCH_BYTES - 256) / 44)
+
+/* For callers that cannot allocate memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): lbm_read_fields
+ * with the same arguments, outputs and result, that allocates nothing.
+ * Its device staging lives in a fixed array of LBM_NOALLOC_SCRATCH_BYTES
+ * per device, which the library reserves when it is loaded on a device and
+ * holds until the process ends; sites of an instance whose fast axis is
+ * exchanged are put in canonical order on the device.  Every call on one
+ * device shares that array (the previous call's contents are overwritten;
+ * what must start at zero is cleared by a kernel, not a memset), so calls
+ * that overlap on one device, from different threads or from contexts with
+ * different streams, race.  Errors: those of lbm_read_fields; LBM_EINVAL if
+ * the instance has more than LBM_NOALLOC_MAX_SITES sites; LBM_ESTATE if
+ * wall or iolet parameters were changed after the last lbm_step or
+ * lbm_read_fields (the update that applies them would allocate), or if the
+ * current device is not the context's. */
+int lbm_read_fields_noalloc(lbm_ctx* ctx, int inst, double* rho, double* u, double* wss,
+                            float* wall_dr);
+
 /* Populations f_i(t) of instance inst, n * 19 doubles, site-major, in the
  * population order above (checkpoint).  Synchronises. */
 int lbm_read_populations(lbm_ctx* ctx, int inst, double* f);

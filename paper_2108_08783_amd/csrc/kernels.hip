@@ -663,11 +663,22 @@ __global__ __launch_bounds__(256) void k_fields(FieldArgs a) {
     acc h[Q];
     gather<DT, I>((const typename Codec<DT>::raw*)a.A, a.np, x, d, h);
     const Mom<acc> m = moments(h);
-    if (a.rho) a.rho[k] = 1.0 + (double)m.drho;
+    double v[3] = {(double)m.ux, (double)m.uy, (double)m.uz};
+    int o = k;
+    if (a.i2c) {
+        o = a.i2c[k];
+        const double t = v[0];
+        v[0] = v[a.axis];
+        v[a.axis] = t;
+    }
+    const double r = 1.0 + (double)m.drho;
+    if (a.bad && !(isfinite(r) && isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2])))
+        atomicOr(a.bad, 1u);
+    if (a.rho) a.rho[o] = r;
     if (a.u) {
-        a.u[3 * k] = (double)m.ux;
-        a.u[3 * k + 1] = (double)m.uy;
-        a.u[3 * k + 2] = (double)m.uz;
+        a.u[3 * (int64_t)o] = v[0];
+        a.u[3 * (int64_t)o + 1] = v[1];
+        a.u[3 * (int64_t)o + 2] = v[2];
     }
 }
 
@@ -704,7 +715,7 @@ __global__ __launch_bounds__(256) void k_wall(WallArgs a) {
     const double tz = c * (S[4] * nx + S[5] * ny + S[2] * nz);
     const double tn = tx * nx + ty * ny + tz * nz;
     const double sx = tx - tn * nx, sy = ty - tn * ny, sz = tz - tn * nz;
-    const int o = x - a.first;
+    const int o = a.i2c ? a.i2c[x - a.first] : x - a.first;
     if (a.wss) a.wss[o] = sqrt(sx * sx + sy * sy + sz * sz);
     if (a.dr) {
         float v = 0.0f;
@@ -838,8 +849,8 @@ __global__ __launch_bounds__(256) void k_copy(u32x4* __restrict__ dst, const u32
         dst[e] = src[e];
 }
 
-__global__ void k_zero_u32(unsigned int* p, int n) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_zero_u32(unsigned int* p, int64_t n) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k < n) p[k] = 0u;
 }
 
@@ -980,7 +991,9 @@ hipError_t launch_copy(void* dst, const void* src, size_t bytes, int nt, hipStre
     return hipGetLastError();
 }
 
-hipError_t launch_zero_u32(unsigned int* p, int n, hipStream_t s) {
+hipError_t launch_zero_u32(unsigned int* p, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    if ((n + 255) / 256 > INT32_MAX) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_zero_u32, dim3(cdiv(n, 256)), dim3(256), 0, s, p, n);
     return hipGetLastError();
 }

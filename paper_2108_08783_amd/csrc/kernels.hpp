@@ -87,6 +87,11 @@ struct FieldArgs {
     double omega;
     double* rho;            // n
     double* u;              // 3n
+    // optional: outputs at canonical positions i2c[k] with velocity
+    // components 0 and `axis` exchanged (NULL: internal order and frame)
+    const int32_t* i2c = nullptr;
+    int32_t axis = 0;
+    unsigned int* bad = nullptr;   // optional: set to 1 if a site is not finite
 };
 
 struct WallArgs {
@@ -105,6 +110,7 @@ struct WallArgs {
     const double* kinv;
     double* wss;            // n (indexed by site - first)
     float* dr;              // n
+    const int32_t* i2c = nullptr;  // optional: write at i2c[site - first]
 };
 
 struct InitArgs {
@@ -144,7 +150,7 @@ hipError_t launch_wall(int dtype, int ibits, const WallArgs& a, hipStream_t s);
 hipError_t launch_init(int dtype, int ibits, const InitArgs& a, hipStream_t s);
 hipError_t launch_read_pop(int dtype, int ibits, const PopArgs& a, hipStream_t s);
 hipError_t launch_delta(int dtype, int ibits, const DeltaArgs& a, hipStream_t s);
-hipError_t launch_zero_u32(unsigned int* p, int n, hipStream_t s);
+hipError_t launch_zero_u32(unsigned int* p, int64_t n, hipStream_t s);
 // out[4 c2i[k] + m] = in[4 k + m'] for k < n: site k of a canonical-order
 // (rho, ux, uy, uz) array goes to internal site c2i[k], with velocity
 // components x and `axis` (1 or 2) exchanged.

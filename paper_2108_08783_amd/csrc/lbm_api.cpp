@@ -57,6 +57,32 @@ std::map<TuneKey, TuneVal> g_tune_cache;
 
 constexpr int GRAPH_STEPS = 128;  // even
 
+// Staging memory of lbm_read_fields_noalloc: one array per device that the
+// library runs on, held until the process ends.  Host code uses only the
+// device address obtained for it with hipGetSymbolAddress (scratch_ptr).
+static __device__ __align__(256) unsigned char scratch[LBM_NOALLOC_SCRATCH_BYTES];
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+// Looks up the device address of `scratch` on the current device, once per
+// device.  Returns nullptr (with the HIP error in *err) on failure.
+void* scratch_ptr(int dev, hipError_t* err) {
+    *err = hipSuccess;
+    if (dev < 0 || dev >= MAX_DEVICES) {
+        *err = hipErrorInvalidDevice;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        *err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (*err != hipSuccess) return nullptr;
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
+}
+
 }  // namespace
 
 struct lbm_ctx {
@@ -107,6 +133,11 @@ struct lbm_ctx {
     int64_t* clock = nullptr;
     unsigned int* maxes = nullptr;
     DevBuf scratch;
+    // per instance whose fast axis is exchanged: internal local site ->
+    // canonical local site, on the device (read-out without host staging)
+    std::vector<int32_t*> i2c_dev;
+    int device = 0;            // the device the context was created on
+    void* noalloc = nullptr;   // device address of that device's staging array
     // state
     int64_t step = 0;
     bool tables_dirty = true, params_dirty = true;
@@ -737,6 +768,17 @@ int lbm_create_geometry_ex(lbm_ctx** out, const lbm_instance_desc* inst, int n_i
         }
     }
     int rc = 0;
+    {
+        hipError_t de = hipGetDevice(&c->device);
+        hipError_t se = de;
+        if (de == hipSuccess) c->noalloc = scratch_ptr(c->device, &se);
+        if (de != hipSuccess || se != hipSuccess) {
+            if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+            delete c;
+            return fail(nullptr, LBM_EDEVICE, "device set-up failed: %s",
+                        hipGetErrorString(de != hipSuccess ? de : se));
+        }
+    }
     const size_t pop_bytes = (size_t)Q * c->np * c->esize;
     rc = rc ? rc : dalloc(c, &c->buf[0], pop_bytes);
     rc = rc ? rc : dalloc(c, &c->buf[1], pop_bytes);
@@ -784,6 +826,21 @@ int lbm_create_geometry_ex(lbm_ctx** out, const lbm_instance_desc* inst, int n_i
     rc = rc ? rc : dalloc(c, (void**)&c->kinv, std::max(1, so) * sizeof(double));
     rc = rc ? rc : dalloc(c, (void**)&c->clock, 2 * sizeof(int64_t));
     rc = rc ? rc : dalloc(c, (void**)&c->maxes, 4 * sizeof(unsigned int));
+    if (rc) {
+        g_last_error = c->err;
+        lbm_destroy(c);
+        return rc;
+    }
+    // internal -> canonical site maps of exchanged instances
+    c->i2c_dev.assign((size_t)n_inst, nullptr);
+    for (int k = 0; k < n_inst && !rc; ++k) {
+        if (!c->axis[k]) continue;
+        const std::vector<int32_t>& m = c->c2i[k];
+        std::vector<int32_t> inv(m.size());
+        for (size_t j = 0; j < m.size(); ++j) inv[(size_t)m[j]] = (int32_t)j;
+        rc = dalloc(c, (void**)&c->i2c_dev[k], inv.size() * 4);
+        rc = rc ? rc : upload(c, c->i2c_dev[k], inv.data(), inv.size() * 4);
+    }
     if (rc) {
         g_last_error = c->err;
         lbm_destroy(c);
@@ -1057,6 +1114,77 @@ int lbm_read_fields(lbm_ctx* c, int inst, double* rho, double* u, double* wss, f
             if (wall_dr) wall_dr[k] = pd[j];
         }
     }
+    return LBM_OK;
+}
+
+int lbm_read_fields_noalloc(lbm_ctx* c, int inst, double* rho, double* u, double* wss,
+                            float* wall_dr) {
+    int rc = check_inst(c, inst);
+    if (rc) return rc;
+    if (c->tables_dirty || c->params_dirty)
+        return fail(c, LBM_ESTATE, "wall or iolet parameters changed since the last step: call "
+                                   "lbm_step or lbm_read_fields first");
+    const InstanceGeom& g = c->plan.inst[inst];
+    const int64_t n = g.n;
+    if (n > LBM_NOALLOC_MAX_SITES)
+        return fail(c, LBM_EINVAL, "instance %d has %lld sites; lbm_read_fields_noalloc takes at most %lld",
+                    inst, (long long)n, (long long)LBM_NOALLOC_MAX_SITES);
+    int dev = -1;
+    HIP_TRY(c, hipGetDevice(&dev));
+    if (dev != c->device)
+        return fail(c, LBM_ESTATE, "current device %d is not the context's device %d", dev, c->device);
+    // staging in the device's static array: flag | rho | u | wss | dr
+    unsigned char* base = (unsigned char*)c->noalloc;
+    unsigned int* bad = (unsigned int*)base;
+    double* s_rho = (double*)(base + 256);
+    double* s_u = s_rho + n;
+    double* s_wss = s_u + 3 * n;
+    float* s_dr = (float*)(s_wss + n);
+    const void* A = c->buf[c->step & 1];
+    const int ax = c->axis[inst];
+    hipError_t e = launch_zero_u32(bad, 1, c->stream);
+    if (e != hipSuccess) return fail(c, LBM_EDEVICE, "launch failed: %s", hipGetErrorString(e));
+    FieldArgs fa{A, nbr_rd(c), c->np, (int32_t)g.offset, (int32_t)n, 1.0 / c->tau, s_rho, s_u};
+    fa.i2c = c->i2c_dev[inst];
+    fa.axis = ax;
+    fa.bad = bad;
+    e = launch_fields(c->dtype, 32, fa, c->stream);
+    if (e != hipSuccess) return fail(c, LBM_EDEVICE, "read-out launch failed: %s", hipGetErrorString(e));
+    if (wss || wall_dr) {
+        // zero by a fill kernel (the wall kernel writes wall sites only)
+        e = launch_zero_u32((unsigned int*)s_wss, 2 * n + n, c->stream);
+        if (e != hipSuccess) return fail(c, LBM_EDEVICE, "launch failed: %s", hipGetErrorString(e));
+        const InstState& st = c->ist[inst];
+        WallArgs wa;
+        wa.A = A;
+        wa.nbr = nbr_rd(c);
+        wa.np = c->np;
+        wa.first = (int32_t)g.offset;
+        wa.nw = (int32_t)(g.wall_end - g.wall_begin);
+        wa.wsite = c->wsite + g.wall_begin;
+        wa.wnormal = c->wnormal + 3 * g.wall_begin;
+        wa.wk = c->wk + g.wall_begin;
+        wa.omega = 1.0 / c->tau;
+        wa.stress_fac = 1.0 - 1.0 / (2.0 * c->tau);
+        wa.dp0 = 1.0 / 3.0 - st.P0;
+        wa.elastic = st.mode == LBM_WALL_ELASTIC;
+        wa.kinv = c->kinv;
+        wa.wss = s_wss;
+        wa.dr = s_dr;
+        wa.i2c = c->i2c_dev[inst];
+        e = launch_wall(c->dtype, 32, wa, c->stream);
+        if (e != hipSuccess) return fail(c, LBM_EDEVICE, "wall read-out launch failed: %s", hipGetErrorString(e));
+    }
+    unsigned int flag = 0;
+    HIP_TRY(c, hipMemcpyAsync(&flag, bad, sizeof(flag), hipMemcpyDeviceToHost, c->stream));
+    if (rho) HIP_TRY(c, hipMemcpyAsync(rho, s_rho, (size_t)n * 8, hipMemcpyDeviceToHost, c->stream));
+    if (u) HIP_TRY(c, hipMemcpyAsync(u, s_u, (size_t)n * 24, hipMemcpyDeviceToHost, c->stream));
+    if (wss) HIP_TRY(c, hipMemcpyAsync(wss, s_wss, (size_t)n * 8, hipMemcpyDeviceToHost, c->stream));
+    if (wall_dr) HIP_TRY(c, hipMemcpyAsync(wall_dr, s_dr, (size_t)n * 4, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (flag)
+        return fail(c, LBM_EDIVERGED, "non-finite field in instance %d (step %lld)", inst,
+                    (long long)c->step);
     return LBM_OK;
 }
 

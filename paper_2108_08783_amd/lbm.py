@@ -32,8 +32,13 @@ EXPORTS = [
     "lbm_write_populations", "lbm_cycle_delta", "lbm_get_info", "lbm_instance_sites",
     "lbm_set_launch", "lbm_autotune", "lbm_plan_export", "lbm_copy_probe",
     "lbm_plan_compressed", "lbm_set_wall_F", "lbm_fast_axis", "lbm_create_geometry_ex",
-    "lbm_uses_caller_resources",
+    "lbm_uses_caller_resources", "lbm_read_fields_noalloc",
 ]
+
+# Staging limit of lbm_read_fields_noalloc (LBM_NOALLOC_SCRATCH_BYTES and
+# LBM_NOALLOC_MAX_SITES in include/lbm.h).
+NOALLOC_SCRATCH_BYTES = 96 << 20
+NOALLOC_MAX_SITES = (NOALLOC_SCRATCH_BYTES - 256) // 44
 
 
 class LbmError(RuntimeError):
@@ -143,6 +148,7 @@ def load():
         "lbm_get_stream": [P, P],
         "lbm_time_steps": [P, L, P],
         "lbm_read_fields": [P, I, P, P, P, P],
+        "lbm_read_fields_noalloc": [P, I, P, P, P, P],
         "lbm_read_populations": [P, I, P],
         "lbm_write_populations": [P, I, P],
         "lbm_cycle_delta": [P, I, P, P],
@@ -285,6 +291,16 @@ def lbm_read_fields(ctx, inst, wss=True, wall_dr=True):
     dr = np.zeros(n, np.float32) if wall_dr else None
     _check(load().lbm_read_fields(ctx, inst, _p(rho), _p(u), _p(w), _p(dr)), ctx)
     return rho, u, w, dr
+
+
+def lbm_read_fields_noalloc(ctx, inst, rho, u, wss=None, wall_dr=None):
+    """lbm_read_fields into caller-owned host arrays (rho[n], u[n,3] float64,
+    optional wss[n] float64, wall_dr[n] float32), with no allocation by the
+    library; any array may be None."""
+    for a, dt in ((rho, np.float64), (u, np.float64), (wss, np.float64), (wall_dr, np.float32)):
+        if a is not None and (a.dtype != dt or not a.flags.c_contiguous):
+            raise TypeError("output arrays must be C-contiguous float64 (float32 for wall_dr)")
+    _check(load().lbm_read_fields_noalloc(ctx, inst, _p(rho), _p(u), _p(wss), _p(wall_dr)), ctx)
 
 
 def lbm_read_populations(ctx, inst):
