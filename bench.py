@@ -1,18 +1,22 @@
 """Throughput benchmark of the elastic-wall D3Q19 update on one MI355X.
 
-Workload (one step = one update of every fluid site, boundary pass included):
-elastic straight cylinder, radius 32, length 512 (1,640,960 fluid sites),
-D3Q19 BGK tau = 0.8, FP32 deviation storage, pulsatile parabolic velocity
-inlet u(t) = 0.02 (1 + 0.5 sin(2 pi t / 4000)), fixed-density outlet,
-stiffness k log-uniform in [1e-3, 1e-1] (seed 1), F = 0.85.
+Workload (one step = one update of every fluid site, boundary links
+included): the synthetic 4-generation Murray artery tree, seed 3
+(7,484,227 fluid sites in a 1200 x 400 x 400 box, 79 stiffness segments,
+48 fixed-density outlets), D3Q19 BGK tau = 0.8, FP32 deviation storage,
+elastic walls (F = 0.5, stiffness log-uniform in [1e-3, 1e-1] per segment),
+pulsatile parabolic velocity inlet u(t) = 0.02 (1 + 0.5 sin(2 pi t / 4000)).
 
-Prints one JSON line: MLUPS (whole job), the HBM roofline of the update
-kernel (algorithmic bytes 2 * 19 * 4 per site per step over the kernel's
-average duration, measured with HIP events on the library's stream), and the
-FP64 CPU oracle timed on a bounded sample of the same workload.  Secondary
-figures (FP16/BF16 storage, bounce-back vs elastic) ride in "secondary".
-``--workload tree`` or ``--workload sweep`` times one of those instead (for
-profiling them on their own; no oracle baseline then).
+Prints one JSON line: MLUPS over exactly --steps timed steps (whole job);
+the HBM roofline of the update kernel (algorithmic bytes 2 * 19 * 4 per site
+per launch over the kernel's average launch duration, HIP events on the
+stream the library launches on, over a window of at least 2048
+graph-replayed launches whatever --steps is); and the FP64 CPU oracle timed
+on a bounded sample of the same workload.  Secondary figures (FP16/BF16
+storage, the 64-instance sweep, bounce-back vs elastic, the cache-resident
+tube, the paper's R = 100 cylinder, the network) ride in "secondary".
+``--workload tube`` or ``--workload sweep`` makes one of those the main line
+(for profiling them on their own; no oracle baseline then).
 """
 from __future__ import annotations
 
@@ -30,6 +34,8 @@ METRIC = ("MLUPS & % of HBM roofline (FP32 vs FP16 storage); cycles-to-periodic,
 PEAK_GBS = 8000.0
 # autotuner trial length of the main run (the other runs use 256 steps)
 MAIN_TUNE_STEPS = 1024
+# launches per roofline window (multiple of the library's 128-step graphs)
+ROOF_MIN_LAUNCHES = 2048
 BYTES_PER_POP = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
 
 
@@ -49,10 +55,11 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-# the main workload: the headline tube, or the tree or the sweep (used to
+# the main workload: the headline tree, or the tube or the sweep (used to
 # profile those on their own)
 WORKLOADS = {
-    "tube": ("tube32", "elastic straight cylinder R=32 L=512, D3Q19 BGK tau=0.8, "
+    "tube": ("tube32", "elastic straight cylinder R=32 L=512 (1,640,960 sites; FP32 working "
+                       "set partly inside the 256 MB Infinity Cache), D3Q19 BGK tau=0.8, "
                        "pulsatile parabolic velocity inlet 0.02(1+0.5 sin(2 pi t/4000)), "
                        "density outlet, k log-uniform [1e-3,1e-1] seed 1, F=0.85"),
     "tree": ("tree", "elastic Murray tree seed 3 (7,484,227 sites), D3Q19 BGK tau=0.8, "
@@ -112,7 +119,17 @@ def copy_probe(gib=1.0, reps=20):
     return out
 
 
+def roof_window(steps):
+    """Launches in a roofline window: at least ROOF_MIN_LAUNCHES, a multiple
+    of 128 (whole graph replays)."""
+    n = max(ROOF_MIN_LAUNCHES, steps)
+    return (n + 127) // 128 * 128
+
+
 def gpu_run(wl, dtype, steps, warmup, bounceback=False, tune=True, launch=None, tune_steps=256):
+    """Creates the lattice, autotunes, warms up, then times exactly `steps`
+    steps (wall clock and HIP events) and, separately, a roofline window of
+    graph-replayed launches (HIP events on the library's stream)."""
     import torch
     from paper_2108_08783_amd import lbm, workloads
     tc = time.perf_counter()
@@ -133,46 +150,48 @@ def gpu_run(wl, dtype, steps, warmup, bounceback=False, tune=True, launch=None, 
     ms = lat.time_steps(steps)          # HIP events on the library stream
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    win = roof_window(steps)
+    roof_ms = lat.time_steps(win)       # graph replays, HIP events
     info = lat.info()
     for k in range(len(wl.geoms)):
         lat.read_fields(k, wss=False, wall_dr=False)  # raises if diverged
     lat.close()
     n = info["n_sites"]
-    print(f"[bench]   {dtype}: create {t_create:.1f}s, tune {t_tune:.1f}s, timed {t1 - t0:.2f}s",
-          file=sys.stderr, flush=True)
+    print(f"[bench]   {dtype}: create {t_create:.1f}s, tune {t_tune:.1f}s, timed {t1 - t0:.3f}s, "
+          f"roofline window {win} launches {roof_ms:.1f} ms", file=sys.stderr, flush=True)
     return dict(n=n, wall_s=t1 - t0, event_ms=ms, info=info,
                 mlups=n * steps / (t1 - t0) / 1e6,
-                launch_us=ms * 1e3 / steps)
+                launch_us=roof_ms * 1e3 / win, window=win)
 
 
 def summary(r, dtype, with_traffic=False):
     ach = 2 * 19 * BYTES_PER_POP[dtype] * r["n"] / (r["launch_us"] * 1e-6) / 1e9
     out = dict(sites=r["n"], mlups=round(r["mlups"], 1), us_per_step=round(r["launch_us"], 2),
                roofline_frac=round(ach / PEAK_GBS, 4), achieved_gbs=round(ach, 1),
+               window_launches=r["window"],
                index_bits=r["info"]["index_bits"], block=r["info"]["block_size"],
                fused=r["info"]["boundary_fused"], boundary_sites=r["info"]["n_boundary"])
     if with_traffic:
-        out["traffic"] = traffic_from_profiles(dtype)
+        out["traffic"] = traffic_from_profiles(dtype, with_traffic)
     return out
 
 
-def cpu_one_thread(target_s=6.0):
-    """The oracle on the same tube with one OpenMP thread, in a child process
-    (the thread count is fixed when the oracle library loads)."""
+def cpu_one_thread(workload, target_s=6.0):
+    """The oracle on the main workload with one OpenMP thread, in a child
+    process (the thread count is fixed when the oracle library loads)."""
     import subprocess
     code = (
         "import json, sys, time; sys.path.insert(0, %r)\n"
         "import bench, oracle\n"
-        "from paper_2108_08783_amd import workloads\n"
-        "wl = workloads.tube32(); g = wl.geoms[0]\n"
+        "wl = bench.make_workload(%r); g = wl.geoms[0]\n"
         "o = oracle.Oracle(g.labels, wl.tau, segment=g.segment, normal=g.normal, iolet_weight=g.iolet_weight)\n"
         "bench.oracle_configure(o, wl); o.step(1)\n"
         "t0 = time.perf_counter(); o.step(1); dt = time.perf_counter() - t0\n"
         "n = max(2, int(%f / max(dt, 1e-6)))\n"
         "t0 = time.perf_counter(); o.step(n); el = time.perf_counter() - t0\n"
         "print(json.dumps(dict(value=o.n * n / el / 1e6, unit='MLUPS', cores=oracle.num_threads(), "
-        "sample='%%d steps of the 1640960-site elastic tube (FP64), %%.1f s' %% (n, el))))\n"
-    ) % (ROOT, target_s)
+        "sample='%%d steps of the %%d-site workload (FP64), %%.1f s' %% (n, o.n, el))))\n"
+    ) % (ROOT, workload, target_s)
     env = dict(os.environ, OMP_NUM_THREADS="1")
     r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
                        check=True)
@@ -180,7 +199,8 @@ def cpu_one_thread(target_s=6.0):
 
 
 def cpu_baseline(wl, target_s=15.0):
-    """The FP64 oracle on the same tube, timed on this host's cores."""
+    """The FP64 oracle on the first instance of the workload, timed on this
+    host's cores over a bounded number of steps."""
     import oracle
     g = wl.geoms[0]
     o = oracle.Oracle(g.labels, wl.tau, segment=g.segment, normal=g.normal,
@@ -196,7 +216,7 @@ def cpu_baseline(wl, target_s=15.0):
     el = time.perf_counter() - t0
     return dict(value=o.n * steps / el / 1e6, unit="MLUPS", cores=oracle.num_threads(),
                 kind="oracle",
-                sample=f"{steps} steps of the same {o.n}-site elastic tube (FP64, OpenMP), "
+                sample=f"{steps} steps of the same {o.n}-site elastic workload (FP64, OpenMP), "
                        f"{el:.1f} s")
 
 
@@ -208,8 +228,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--dtype", default="f32")
-    ap.add_argument("--workload", default="tube", choices=sorted(WORKLOADS),
-                    help="main workload (default: the tube the headline is quoted on)")
+    ap.add_argument("--workload", default="tree", choices=sorted(WORKLOADS),
+                    help="main workload (default: the tree the headline is quoted on)")
     ap.add_argument("--launch", default=None,
                     help="JSON launch configuration instead of autotuning")
     ap.add_argument("--probe-copy", action="store_true",
@@ -231,43 +251,63 @@ def main():
     from paper_2108_08783_amd import workloads
     launch = json.loads(args.launch) if args.launch else None
     dtype = args.dtype
-    tube = workloads.tube32()
-    main_wl = tube if args.workload == "tube" else make_workload(args.workload)
+    main_wl = make_workload(args.workload)
     main_run = gpu_run(main_wl, dtype, args.steps, args.warmup, launch=launch,
                        tune_steps=MAIN_TUNE_STEPS)
-    if main_wl is not tube:
-        del main_wl
-    print(f"[bench] {args.workload} {dtype}: {main_run['mlups']:.0f} MLUPS, "
-          f"{main_run['launch_us']:.2f} us/step", file=sys.stderr, flush=True)
+    print(f"[bench] {args.workload} {dtype}: {main_run['mlups']:.0f} MLUPS over {args.steps} steps, "
+          f"{main_run['launch_us']:.2f} us per launch over {main_run['window']}",
+          file=sys.stderr, flush=True)
     n = main_run["n"]
     alg_bytes = 2 * 19 * BYTES_PER_POP[dtype] * n
     achieved = alg_bytes / (main_run["launch_us"] * 1e-6) / 1e9
     tr = traffic_from_profiles(dtype, args.workload)
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / PEAK_GBS, 4), traffic=tr)
+                    frac=round(achieved / PEAK_GBS, 4), traffic=tr,
+                    kernel="k_step", window_launches=main_run["window"], graph_replayed=True,
+                    us_per_launch=round(main_run["launch_us"], 3),
+                    algorithmic_bytes_per_launch=alg_bytes)
 
     secondary = {}
     if not args.no_secondary:
         secondary["copy_probe"] = copy_probe()
-        for dt in ("f16", "bf16"):
-            r = gpu_run(tube, dt, args.steps, args.warmup)
-            secondary["tube_" + dt] = summary(r, dt, with_traffic=True)
-            print(f"[bench] tube {dt}: {r['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
-        bb = gpu_run(tube, dtype, args.steps, args.warmup, bounceback=True)
-        secondary["tube_bounceback_" + dtype] = dict(
-            summary(bb, dtype), elastic_over_bb_time=round(main_run["launch_us"] / bb["launch_us"], 4))
-        tree = workloads.tree()
-        for dt in ("f32", "f16", "bf16"):
-            r = gpu_run(tree, dt, args.steps // 4, args.warmup)
-            secondary["tree_" + dt] = summary(r, dt)
-            print(f"[bench] tree {dt}: {r['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
-        del tree
-        sw = workloads.sweep()
+        sec_steps = min(args.steps, 1024)
+        if args.workload != "tree":
+            tree = workloads.tree()
+        else:
+            tree = main_wl
+        for dt in ("f16", "bf16", "f32"):
+            if args.workload == "tree" and dt == dtype:
+                continue
+            r = gpu_run(tree, dt, sec_steps, args.warmup)
+            secondary["tree_" + dt] = summary(r, dt, with_traffic="tree")
+            print(f"[bench] tree {dt}: {r['launch_us']:.2f} us per launch", file=sys.stderr,
+                  flush=True)
+        bb = gpu_run(tree, "f32", sec_steps, args.warmup, bounceback=True)
+        elastic_us = (main_run if (args.workload == "tree" and dtype == "f32")
+                      else gpu_run(tree, "f32", sec_steps, args.warmup))["launch_us"]
+        secondary["tree_bounceback_f32"] = dict(
+            summary(bb, "f32"), elastic_over_bb_time=round(elastic_us / bb["launch_us"], 4))
+        if tree is not main_wl:
+            del tree
+        sw = main_wl if args.workload == "sweep" else workloads.sweep()
         for dt in ("f16", "f32"):
-            r = gpu_run(sw, dt, args.steps // 8, args.warmup // 4)
-            secondary["sweep64_" + dt] = summary(r, dt)
-            print(f"[bench] sweep {dt}: {r['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
-        del sw
+            if args.workload == "sweep" and dt == dtype:
+                continue
+            r = gpu_run(sw, dt, min(sec_steps, 512), args.warmup // 4)
+            secondary["sweep64_" + dt] = summary(r, dt, with_traffic="sweep")
+            print(f"[bench] sweep {dt}: {r['launch_us']:.2f} us per launch", file=sys.stderr,
+                  flush=True)
+        if sw is not main_wl:
+            del sw
+        tube = main_wl if args.workload == "tube" else workloads.tube32()
+        for dt in ("f32", "f16"):
+            if args.workload == "tube" and dt == dtype:
+                continue
+            r = gpu_run(tube, dt, sec_steps, args.warmup)
+            secondary["tube_cache_resident_" + dt] = summary(r, dt, with_traffic="tube")
+            print(f"[bench] tube {dt}: {r['launch_us']:.2f} us per launch", file=sys.stderr,
+                  flush=True)
+        del tube
         # the paper's R = 100 dx verification cylinder (41.9M sites, 6.4 GB
         # of FP32 populations): 1000 iterations beside its Table 1 entry
         from paper_2108_08783_amd import verification
@@ -279,27 +319,18 @@ def main():
             paper_elastic_s_per_1000=row["paper_elastic_s"], paper_cores=6000)
         print(f"[bench] paper cylinder R=100: {row['elastic_s']:.3f} s per 1000 iterations",
               file=sys.stderr, flush=True)
-        # the warm-start network on one sample per tree site: forward pass
-        # (bf16 MFMA; HBM-bound at 4,144 B per sample), inference (2,096 B per
-        # sample: no pre-activations kept) and training step
+        # the warm-start network on one sample per tree site
         from paper_2108_08783_amd import mlp
         nb = mlp.bench(7_484_227, reps=5)
-        fwd_gbs = 4144 * nb["samples"] / (nb["forward"]["ms"] * 1e-3) / 1e9
-        inf_gbs = 2096 * nb["samples"] / (nb["infer"]["ms"] * 1e-3) / 1e9
-        secondary["mlp_7M_samples"] = dict(
-            nb, forward_achieved_gbs=round(fwd_gbs, 1),
-            forward_roofline_frac=round(fwd_gbs / PEAK_GBS, 4),
-            infer_achieved_gbs=round(inf_gbs, 1), infer_roofline_frac=round(inf_gbs / PEAK_GBS, 4))
-        print(f"[bench] network: forward {nb['forward']['ms']:.2f} ms, inference "
-              f"{nb['infer']['ms']:.2f} ms, training step {nb['train_step']['ms']:.2f} ms",
-              file=sys.stderr, flush=True)
+        secondary["mlp_7M_samples"] = nb
+        print(f"[bench] network: {json.dumps(nb)}", file=sys.stderr, flush=True)
 
     cpu = None
-    if not args.no_cpu and args.workload == "tube":
-        cpu = cpu_baseline(tube)
+    if not args.no_cpu and args.workload == "tree":
+        cpu = cpu_baseline(main_wl)
         print(f"[bench] oracle: {cpu['value']:.1f} MLUPS on {cpu['cores']} threads",
               file=sys.stderr, flush=True)
-        secondary["oracle_1_thread"] = cpu_one_thread()
+        secondary["oracle_1_thread"] = cpu_one_thread(args.workload)
         print(f"[bench] oracle, 1 thread: {secondary['oracle_1_thread']['value']:.2f} MLUPS",
               file=sys.stderr, flush=True)
 
@@ -315,7 +346,7 @@ def main():
                     index_bits=info["index_bits"], block=info["block_size"],
                     xcd_remap=info["xcd_remap"], nontemporal=info["nontemporal"],
                     boundary_fused=info["boundary_fused"],
-                    graph_steps=128, parallelism="single GPU",
+                    timed_steps_graph_replayed=args.steps >= 128, parallelism="single GPU",
                     autotune_trial_steps=MAIN_TUNE_STEPS),
         roofline=roofline,
         cpu_baseline=cpu,
