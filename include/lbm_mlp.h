@@ -66,6 +66,17 @@ int mlp_forward(const mlp_shape* s, const float* params, const uint16_t* wb, int
 int mlp_infer(const mlp_shape* s, const float* params, const uint16_t* wb, int64_t n,
               const uint16_t* X, float* Z, uint16_t* A, void* stream);
 
+/* Inference of n samples in one launch: Y (n x n_out FP32, row-major,
+ * 16-byte aligned) from X, with every layer fused (weights resident in LDS,
+ * activations in registers), so only X and Y touch memory.  Needs width =
+ * 128, n_in <= 32, n_out <= 16 and depth <= 5 (else -1; mlp_infer covers
+ * other shapes).  Hidden biases enter as the accumulators' initial values
+ * and SiLU uses the hardware reciprocal, so Y agrees with mlp_forward's to
+ * FP32 rounding (and bf16 rounding of a hidden activation where that
+ * differs), not bit for bit. */
+int mlp_infer_fused(const mlp_shape* s, const float* params, const uint16_t* wb, int64_t n,
+                    const uint16_t* X, float* Y, void* stream);
+
 /* Backward pass for the loss gradient dY (n x n_out FP32) of the forward
  * pass that produced Z and A: writes the gradient of every parameter into
  * grad (FP32, parameter layout).  Workspaces: work_f of

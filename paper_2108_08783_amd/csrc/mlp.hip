@@ -420,6 +420,228 @@ __global__ void k_adam(int64_t n, float* __restrict__ p, uint16_t* __restrict__ 
     pb[e] = f2bf(pe);
 }
 
+// ---------------------------------------------------------------------------
+// Fused inference: every layer of one network in one kernel.  The bf16
+// weights (about 108 KB for 16 -> 128 x 4 -> 4) stay in LDS for the whole
+// launch and the activations never leave registers, so HBM sees only the
+// features in and the outputs out (32 + 16 bytes per sample).
+//
+// Each layer is computed transposed, out^T (out x S) = W (out x in) in^T
+// (in x S), with MFMA 16x16x32 bf16: A = a 16 x 32 block of W (read from
+// LDS, stored there in operand order so that lane l's 16 bytes are at
+// l * 16 of a 1 KB block), B = a 32 x 16 block of in^T (16 samples), D = a
+// 16 x 16 block of out^T.  Lane l holds D rows 4 (l / 16) + 0..3 (four
+// output features) of column l % 16 (one sample), and the next layer's B
+// operand wants rows 8 (l / 16) + 0..7 of the same column: after the
+// epilogue (bias, SiLU, bf16 pairs) two output tiles become one K tile of
+// the next layer through two lane swaps across 32- and 16-lane halves
+// (v_permlane32_swap, v_permlane16_swap), with no LDS round trip.
+namespace fused {
+constexpr int W = 128;            // hidden width
+constexpr int NT = W / 16;        // output tiles of a hidden layer
+constexpr int NK = W / 32;        // K tiles of a hidden layer
+constexpr int J = 4;              // 16-sample tiles per wave and step
+constexpr int THREADS = 512;
+constexpr int MAX_DEPTH = 5;
+
+template <int DEPTH>
+struct Lds {
+    // operand blocks: layer 0 (NT x 1), hidden layers (NT x NK each), head (1 x NK)
+    uint4 w[(NT + (DEPTH - 1) * NT * NK + NK) * 64];
+    float bias[DEPTH * W + 16];
+};
+
+__device__ __forceinline__ int block_of(int layer, int o, int k) {
+    return layer == 0 ? o : NT + (layer - 1) * NT * NK + o * NK + k;
+}
+
+// silu(z) = z / (1 + e^-z) with the hardware reciprocal (1 ulp)
+__device__ __forceinline__ float silu_fast(float z) {
+    return z * __builtin_amdgcn_rcpf(1.0f + __expf(-z));
+}
+
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned pack_bf16(float x, float y) {  // round to nearest even
+    const f32x2 v = {x, y};
+    return __builtin_bit_cast(unsigned, __builtin_convertvector(v, bf16x2));
+}
+
+// Two output tiles (h = 0, 1) of one 16-sample tile, after bias and SiLU,
+// as the next layer's B operand: components {a, b} of the first and the
+// second source row group.
+__device__ __forceinline__ bf16x8 to_operand(const f32x4& d0, const f32x4& d1) {
+    const unsigned a0 = pack_bf16(silu_fast(d0[0]), silu_fast(d0[1]));
+    const unsigned b0 = pack_bf16(silu_fast(d0[2]), silu_fast(d0[3]));
+    const unsigned a1 = pack_bf16(silu_fast(d1[0]), silu_fast(d1[1]));
+    const unsigned b1 = pack_bf16(silu_fast(d1[2]), silu_fast(d1[3]));
+    const auto ra = __builtin_amdgcn_permlane32_swap(a0, a1, false, false);
+    const auto qa = __builtin_amdgcn_permlane16_swap(ra[0], ra[1], false, false);
+    const auto rb = __builtin_amdgcn_permlane32_swap(b0, b1, false, false);
+    const auto qb = __builtin_amdgcn_permlane16_swap(rb[0], rb[1], false, false);
+    const u32x4 v = {(unsigned)qa[0], (unsigned)qb[0], (unsigned)qa[1], (unsigned)qb[1]};
+    return __builtin_bit_cast(bf16x8, v);
+}
+
+template <int DEPTH>
+__global__ __launch_bounds__(THREADS) void k_mlp_fused(int64_t n, int n_in, int n_out,
+                                                       const uint16_t* __restrict__ wb,
+                                                       const float* __restrict__ params,
+                                                       const uint16_t* __restrict__ X,
+                                                       float* __restrict__ Y, int vec_x) {
+    __shared__ Lds<DEPTH> L;
+    const int t = threadIdx.x;
+    // ---- weights and biases into LDS, in operand order, zero padded
+    constexpr int NBLK = NT + (DEPTH - 1) * NT * NK + NK;
+    for (int c = t; c < NBLK * 64; c += THREADS) {
+        const int blk = c >> 6, lane = c & 63;
+        int layer, o, k;
+        if (blk < NT) {
+            layer = 0; o = blk; k = 0;
+        } else if (blk < NT + (DEPTH - 1) * NT * NK) {
+            const int b = blk - NT;
+            layer = 1 + b / (NT * NK); o = (b % (NT * NK)) / NK; k = b % NK;
+        } else {
+            layer = DEPTH; o = 0; k = blk - NT - (DEPTH - 1) * NT * NK;
+        }
+        const int in = layer == 0 ? n_in : W, out = layer == DEPTH ? n_out : W;
+        int64_t off = 0;   // W_layer offset in the parameter layout
+        for (int q = 0; q < layer; ++q) {
+            const int iq = q == 0 ? n_in : W;
+            off += (int64_t)iq * W + W;
+        }
+        const int r = 16 * o + (lane & 15), k0 = 32 * k + 8 * (lane >> 4);
+        union { uint4 v; uint16_t h[8]; } u;
+        u.v = make_uint4(0u, 0u, 0u, 0u);
+        if (r < out) {
+            const uint16_t* src = wb + off + (int64_t)r * in + k0;
+            if (k0 + 8 <= in && ((uintptr_t)src & 15) == 0) {
+                u.v = *(const uint4*)src;
+            } else {
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    if (k0 + q < in) u.h[q] = src[q];
+            }
+        }
+        L.w[c] = u.v;
+    }
+    for (int c = t; c < DEPTH * W + 16; c += THREADS) {
+        const int layer = c < DEPTH * W ? c / W : DEPTH, j = c < DEPTH * W ? c % W : c - DEPTH * W;
+        const int out = layer == DEPTH ? n_out : W;
+        int64_t off = 0;   // b_layer offset: W_0 b_0 ... W_layer
+        for (int q = 0; q < layer; ++q) off += (int64_t)(q == 0 ? n_in : W) * W + W;
+        off += (int64_t)(layer == 0 ? n_in : W) * out;
+        L.bias[c] = j < out ? params[off + j] : 0.0f;
+    }
+    __syncthreads();
+
+    const int wave = t >> 6, lane = t & 63, g = lane >> 4, li = lane & 15;
+    const int64_t nwaves = (int64_t)gridDim.x * (THREADS / 64);
+    for (int64_t grp = (int64_t)blockIdx.x * (THREADS / 64) + wave; grp * (16 * J) < n;
+         grp += nwaves) {
+        const int64_t s0 = grp * (16 * J);
+        bf16x8 B[NK][J];
+        // ---- layer 0: features k = 8 g + 0..7 of sample s0 + 16 j + li (K padded to 32)
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const int64_t sm = s0 + 16 * j + li;
+            union { uint4 v; uint16_t h[8]; } u;
+            u.v = make_uint4(0u, 0u, 0u, 0u);
+            if (sm < n && 8 * g < n_in) {
+                const uint16_t* src = X + sm * n_in + 8 * g;
+                if (vec_x && 8 * g + 8 <= n_in) {
+                    u.v = *(const uint4*)src;
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 8; ++q)
+                        if (8 * g + q < n_in) u.h[q] = src[q];
+                }
+            }
+            B[0][j] = __builtin_bit_cast(bf16x8, u.v);
+        }
+        bf16x8 Bn[NK][J];
+#pragma unroll
+        for (int p = 0; p < NK; ++p) {
+            f32x4 acc[2][J];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const float4 b4 = *(const float4*)&L.bias[16 * (2 * p + h) + 4 * g];
+                const bf16x8 A = __builtin_bit_cast(bf16x8, L.w[block_of(0, 2 * p + h, 0) * 64 + lane]);
+#pragma unroll
+                for (int j = 0; j < J; ++j) {
+                    acc[h][j] = f32x4{b4.x, b4.y, b4.z, b4.w};
+                    acc[h][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B[0][j], acc[h][j], 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < J; ++j) Bn[p][j] = to_operand(acc[0][j], acc[1][j]);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        // ---- hidden layers
+#pragma unroll
+        for (int l = 1; l < DEPTH; ++l) {
+#pragma unroll
+            for (int p = 0; p < NK; ++p)
+#pragma unroll
+                for (int j = 0; j < J; ++j) B[p][j] = Bn[p][j];
+#pragma unroll
+            for (int p = 0; p < NK; ++p) {
+                f32x4 acc[2][J];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const float4 b4 = *(const float4*)&L.bias[l * W + 16 * (2 * p + h) + 4 * g];
+#pragma unroll
+                    for (int j = 0; j < J; ++j) acc[h][j] = f32x4{b4.x, b4.y, b4.z, b4.w};
+                }
+#pragma unroll
+                for (int k = 0; k < NK; ++k)
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const bf16x8 A =
+                            __builtin_bit_cast(bf16x8, L.w[block_of(l, 2 * p + h, k) * 64 + lane]);
+#pragma unroll
+                        for (int j = 0; j < J; ++j)
+                            acc[h][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B[k][j], acc[h][j], 0, 0, 0);
+                    }
+#pragma unroll
+                for (int j = 0; j < J; ++j) Bn[p][j] = to_operand(acc[0][j], acc[1][j]);
+                // keep the scheduler from hoisting the next pair's operand
+                // reads over this one (they would all be live at once)
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        // ---- output layer (n_out <= 16 outputs in one tile, no activation)
+        f32x4 y[J];
+        {
+            const float4 b4 = *(const float4*)&L.bias[DEPTH * W + 4 * g];
+#pragma unroll
+            for (int j = 0; j < J; ++j) y[j] = f32x4{b4.x, b4.y, b4.z, b4.w};
+#pragma unroll
+            for (int k = 0; k < NK; ++k) {
+                const bf16x8 A = __builtin_bit_cast(bf16x8, L.w[(NT + (DEPTH - 1) * NT * NK + k) * 64 + lane]);
+#pragma unroll
+                for (int j = 0; j < J; ++j)
+                    y[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, Bn[k][j], y[j], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const int64_t sm = s0 + 16 * j + li;
+            if (sm >= n) continue;
+            if (n_out == 4) {
+                if (g == 0) *(float4*)(Y + sm * 4) = make_float4(y[j][0], y[j][1], y[j][2], y[j][3]);
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (4 * g + q < n_out) Y[sm * n_out + 4 * g + q] = y[j][q];
+            }
+        }
+    }
+}
+}  // namespace fused
+
 inline unsigned nb(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 // blocks of k_gemm for an M x N product (one per 64 x 64 tile)
@@ -624,6 +846,39 @@ int mlp_infer(const mlp_shape* s, const float* params, const uint16_t* wb, int64
         x = Al;
     }
     return 0;
+}
+
+int mlp_infer_fused(const mlp_shape* s, const float* params, const uint16_t* wb, int64_t n,
+                    const uint16_t* X, float* Y, void* stream) {
+    if (!valid(s) || n < 0) return err("mlp_infer_fused: bad arguments");
+    if (s->width != fused::W || s->n_in > 32 || s->n_out > 16 || s->depth > fused::MAX_DEPTH)
+        return err("mlp_infer_fused: needs width 128, n_in <= 32, n_out <= 16, depth <= 5");
+    if (n == 0) return 0;
+    if (!params || !wb || !X || !Y) return err("mlp_infer_fused: bad arguments");
+    if ((uintptr_t)Y & 15) return err("mlp_infer_fused: Y must be 16-byte aligned");
+    static int n_cu = 0;
+    if (!n_cu) {
+        int dev = 0;
+        int rc = check(hipGetDevice(&dev));
+        if (rc) return rc;
+        rc = check(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+        if (rc) return rc;
+    }
+    // one block per compute unit (the weights fill most of its LDS), each
+    // wave walking over groups of 64 samples
+    const int64_t groups = (n + 16 * fused::J - 1) / (16 * fused::J);
+    const int64_t per_block = fused::THREADS / 64;
+    const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(n_cu, (groups + per_block - 1) / per_block));
+    const int vec_x = ((uintptr_t)X & 15) == 0 && (s->n_in & 7) == 0;
+    hipStream_t st = (hipStream_t)stream;
+    switch (s->depth) {
+        case 1: hipLaunchKernelGGL(fused::k_mlp_fused<1>, dim3(blocks), dim3(fused::THREADS), 0, st, n, s->n_in, s->n_out, wb, params, X, Y, vec_x); break;
+        case 2: hipLaunchKernelGGL(fused::k_mlp_fused<2>, dim3(blocks), dim3(fused::THREADS), 0, st, n, s->n_in, s->n_out, wb, params, X, Y, vec_x); break;
+        case 3: hipLaunchKernelGGL(fused::k_mlp_fused<3>, dim3(blocks), dim3(fused::THREADS), 0, st, n, s->n_in, s->n_out, wb, params, X, Y, vec_x); break;
+        case 4: hipLaunchKernelGGL(fused::k_mlp_fused<4>, dim3(blocks), dim3(fused::THREADS), 0, st, n, s->n_in, s->n_out, wb, params, X, Y, vec_x); break;
+        default: hipLaunchKernelGGL(fused::k_mlp_fused<5>, dim3(blocks), dim3(fused::THREADS), 0, st, n, s->n_in, s->n_out, wb, params, X, Y, vec_x); break;
+    }
+    return check(hipGetLastError());
 }
 
 int mlp_backward(const mlp_shape* s, const uint16_t* wb, int64_t n, const uint16_t* X,

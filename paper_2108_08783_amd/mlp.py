@@ -18,7 +18,7 @@ from . import lbm
 
 MLP_EXPORTS = ["mlp_param_count", "mlp_act_floats", "mlp_act_bf16", "mlp_gemm_bf16",
                "mlp_forward", "mlp_infer", "mlp_backward", "mlp_mse", "mlp_mse_partials", "mlp_adam",
-               "mlp_to_bf16", "mlp_last_error"]
+               "mlp_to_bf16", "mlp_last_error", "mlp_infer_fused"]
 
 
 class Shape(ctypes.Structure):
@@ -40,6 +40,7 @@ def load():
         "mlp_gemm_bf16": ([I, I, I, P, I, I, P, I, I, P, I, I, P], I),
         "mlp_forward": ([P, P, P, L, P, P, P, P], I),
         "mlp_infer": ([P, P, P, L, P, P, P, P], I),
+        "mlp_infer_fused": ([P, P, P, L, P, P, P], I),
         "mlp_backward": ([P, P, L, P, P, P, P, P, P, P, P], I),
         "mlp_mse": ([L, I, P, P, P, P, P, P, P], I), "mlp_mse_partials": ([L, I], L),
         "mlp_adam": ([L, P, P, P, P, P, F, F, F, F, L, P], I),
@@ -90,6 +91,11 @@ def mlp_forward(shape, params, wb, n, X, Z, A):
 def mlp_infer(shape, params, wb, n, X, Z, A):
     _check(load().mlp_infer(ctypes.byref(shape), _ptr(params), _ptr(wb), n, _ptr(X), _ptr(Z),
                               _ptr(A), _stream()))
+
+
+def mlp_infer_fused(shape, params, wb, n, X, Y):
+    _check(load().mlp_infer_fused(ctypes.byref(shape), _ptr(params), _ptr(wb), n, _ptr(X), _ptr(Y),
+                                  _stream()))
 
 
 def mlp_backward(shape, wb, n, X, Z, A, dY, grad, work_f, work_b):
@@ -183,6 +189,17 @@ class Net:
         off = n * self.shape.depth * self.shape.width
         return self.Z[off:off + n * self.shape.n_out].view(n, self.shape.n_out)
 
+    def infer_fused(self, Xb, out=None):
+        """Output of every layer in one fused launch (weights in LDS,
+        activations in registers): FP32 tensor [n, n_out], equal to forward's
+        to FP32 rounding.  Needs width 128, n_in <= 32, n_out <= 16."""
+        import torch
+        n = Xb.shape[0]
+        Y = out if out is not None else torch.empty((n, self.shape.n_out), dtype=torch.float32,
+                                                    device=self.params.device)
+        mlp_infer_fused(self.shape, self.params, self.wb, n, Xb, Y)
+        return Y
+
     def backward(self, Xb, dY):
         n = Xb.shape[0]
         mlp_backward(self.shape, self.wb, n, Xb, self.Z, self.A, dY, self.grad, self.work_f,
@@ -211,7 +228,7 @@ def flops_per_site(n_in=16, width=128, depth=4, n_out=4):
 
 
 def bench(n=7_484_227, reps=10, seed=0):
-    """Forward pass, inference pass and training step of the default network
+    """Forward pass, inference pass, fused inference and training step of the default network
     on n samples of random features, timed with HIP events on torch's
     current stream; returns a dict of milliseconds and rates."""
     import torch
@@ -220,7 +237,9 @@ def bench(n=7_484_227, reps=10, seed=0):
     X = net.to_bf16(torch.randn(n, net.shape.n_in, device="cuda", generator=g))
     T = torch.randn(n, net.shape.n_out, device="cuda", generator=g)
     out = dict(samples=n, flop_per_sample=flops_per_site())
+    Yf = torch.empty((n, net.shape.n_out), dtype=torch.float32, device="cuda")
     for name, fn in (("forward", lambda: net.forward(X)), ("infer", lambda: net.infer(X)),
+                     ("infer_fused", lambda: net.infer_fused(X, Yf)),
                      ("train_step", lambda: net.train_step(X, T, lr=1e-4))):
         fn()
         torch.cuda.synchronize()
@@ -232,7 +251,9 @@ def bench(n=7_484_227, reps=10, seed=0):
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / reps
         flop = out["flop_per_sample"] * n * (3 if name == "train_step" else 1)
-        out[name] = dict(ms=round(ms, 3), tflops=round(flop / (ms * 1e-3) / 1e12, 2))
+        tflops = flop / (ms * 1e-3) / 1e12
+        out[name] = dict(ms=round(ms, 3), tflops=round(tflops, 2),
+                         frac_of_bf16_dense_peak=round(tflops / 2500.0, 4))
         print(f"[mlp] {name}: {ms:.3f} ms for {n} samples, {flop / (ms * 1e-3) / 1e12:.1f} TFLOP/s",
               file=sys.stderr, flush=True)
     return out

@@ -540,7 +540,7 @@ def predict(net, geo, frame: SiteFrame, params, phase, nu=0.1, chunk=1 << 20, us
             # trust region: the correction to the prior is at most one output
             # unit (u0 in velocity, 10 u0 in density), and none at sites
             # whose features lie outside the training range
-            dY = np.clip(net.infer(xb).cpu().numpy(), -TRUST, TRUST)
+            dY = np.clip(net.infer_fused(xb).cpu().numpy(), -TRUST, TRUST)
             Y[s:s + chunk] += dY * ok[s:s + chunk, None]
     return assemble(frame, Y, u0)
 

@@ -155,3 +155,50 @@ def test_training_reduces_loss():
     for _ in range(400):
         last = net.train_step(Xb, Tt, lr=2e-3)
     assert last.item() < first / 10
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 1000, 70001])
+def test_fused_inference_matches_forward_and_reference(n):
+    """mlp_infer_fused (every layer in one launch, weights in LDS, operands
+    passed between layers by lane swaps) against the layer-by-layer forward
+    pass on the same bf16 weights and inputs (FP32 rounding order and SiLU
+    reciprocal differ, so a hidden activation may round to the neighbouring
+    bf16 value: held to 5e-3 of the output range) and against the FP64
+    reference (1e-2), for ragged sample counts."""
+    import torch
+    net, p, X, Xb, d = _net_and_ref(n=n)
+    Yf = net.forward(Xb).clone()
+    Y = torch.full((n, 4), float("nan"), dtype=torch.float32, device="cuda")
+    net.infer_fused(Xb, Y)
+    torch.cuda.synchronize()
+    Yn = Y.cpu().numpy()
+    assert np.isfinite(Yn).all()
+    diff = np.abs(Yn - Yf.cpu().numpy()).max() / np.abs(Yf.cpu().numpy()).max()
+    print(f"MLP fused vs forward {diff:.3e}", flush=True)
+    assert diff <= 5e-3
+    Yr, _ = M.forward(p, X, d)
+    assert _rel(Yn, Yr) <= 1e-2
+
+
+@pytest.mark.parametrize("dims", [(7, 128, 2, 3), (32, 128, 5, 16), (16, 128, 1, 1)])
+def test_fused_inference_other_shapes(dims):
+    """Input widths that are not a multiple of 8 (element-wise staging),
+    1 to 5 hidden layers and 1 to 16 outputs, against the FP64 reference."""
+    import torch
+    net, p, X, Xb, d = _net_and_ref(n=777, dims=dims, seed=5)
+    Y = net.infer_fused(Xb)
+    torch.cuda.synchronize()
+    Yr, _ = M.forward(p, X, d)
+    assert _rel(Y.cpu().numpy(), Yr) <= 1e-2
+
+
+def test_fused_inference_rejects_unsupported_shapes():
+    import torch
+    from paper_2108_08783_amd import mlp
+    net = mlp.Net(n_in=16, width=64, depth=2, n_out=4, seed=1)
+    Xb = net.to_bf16(torch.zeros(10, 16, device="cuda"))
+    with pytest.raises(RuntimeError):
+        net.infer_fused(Xb)
+    net = mlp.Net(seed=1)
+    Y = net.infer_fused(torch.zeros((0, 16), dtype=torch.bfloat16, device="cuda"))
+    assert Y.shape == (0, 4)
