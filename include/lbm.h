@@ -72,9 +72,14 @@ enum lbm_dtype { LBM_F64 = 0, LBM_F32 = 1, LBM_F16DEV = 2, LBM_BF16DEV = 3 };
 enum lbm_wall_mode { LBM_WALL_BOUNCEBACK = 0, LBM_WALL_ELASTIC = 1 };
 
 /* Inlet/outlet kind (Sec. 3): a DENSITY iolet prescribes rho and keeps the
- * fluid node's velocity, a VELOCITY iolet prescribes u = weight * value * dir
- * and keeps the fluid node's density.  Both write the link's post-collision
- * value as feq(prescribed) + (1 - 1/tau) fneq(fluid node). */
+ * fluid node's velocity (only its component along the iolet's inward normal
+ * n, when n is given), a VELOCITY iolet prescribes u = weight * value * dir
+ * and keeps the fluid node's density.  Both set the iolet node to the
+ * equilibrium at those moments (zeroth order: unlike the elastic wall, no
+ * non-equilibrium part is carried over).  Without the non-equilibrium part,
+ * and with the tangential velocity removed at density iolets, the paper's
+ * R = 50 cylinder stays stable at its tau = 0.537; with either kept, it
+ * diverges there. */
 enum lbm_iolet_kind { LBM_IOLET_DENSITY = 0, LBM_IOLET_VELOCITY = 1 };
 
 /* Voxel labels. */
@@ -211,10 +216,12 @@ int lbm_set_wall_F(lbm_ctx* ctx, int inst, const double* F_per_segment, int n_se
 /* Drive of iolet id of instance inst (Sec. 3).  value(t) = a0 (1 + amp
  * sin(2 pi t / period + phase)), t = steps since the instance's last
  * lbm_init_fields; amp = 0 gives a steady value (period is then ignored,
- * otherwise period > 0).  DENSITY: value is rho.  VELOCITY: the prescribed
- * velocity at fluid site x is iolet_weight(x) * value(t) * dir, dir (3
- * doubles) the unit direction into the vessel.  Every iolet present in the
- * labels must be set before lbm_step.  Errors: LBM_EINVAL. */
+ * otherwise period > 0).  DENSITY: value is rho; dir, if not NULL and not
+ * zero, is the iolet's inward normal n (normalised here): only the fluid
+ * node's velocity along n enters the iolet node.  VELOCITY: the
+ * prescribed velocity at fluid site x is iolet_weight(x) * value(t) * dir,
+ * dir (3 doubles) the unit direction into the vessel.  Every iolet present
+ * in the labels must be set before lbm_step.  Errors: LBM_EINVAL. */
 int lbm_set_iolet(lbm_ctx* ctx, int inst, int id, int kind, double a0, double amp,
                   double period, double phase, const double* dir);
 

@@ -11,7 +11,10 @@ independently of ``lbm_oracle.c``:
     LBE_SRT as printed), rather than the oracle's pull form;
   * the elastic wall velocity uses the combined form U_w = s U_f with
     s = (F + Delta r - 1)/Delta r (Sec. 2.3, equal to the interpolation form
-    for Delta x = 1).
+    for Delta x = 1);
+  * an iolet link takes the equilibrium at the prescribed moment and the
+    fluid node's other moment, at a density iolet with a given inward normal
+    only the velocity along it (Sec. 3, zeroth-order reading).
 
 Populations are addressed by velocity vector, so the caller's direction order
 does not matter.
@@ -79,12 +82,18 @@ def step(labels, f, tau, *, mode, F, P0, k_seg, segment, iolets, iolet_weight, t
                 val = io["a0"]
                 if io["amp"] != 0.0:
                     val *= 1.0 + io["amp"] * math.sin(2 * math.pi * t / io["period"] + io["phase"])
-                if io["kind"] == 0:
-                    new[(x, y, z)][c] = _feq(w, c, val, u) + (1 - omega) * fneq
+                d = io.get("direction")
+                nn = math.sqrt(sum(a * a for a in d)) if d is not None else 0.0
+                if io["kind"] == 0 and nn > 0.0:
+                    nv = [a / nn for a in d]
+                    un = sum(u[a] * nv[a] for a in range(3))
+                    new[(x, y, z)][c] = _feq(w, c, val, [un * a for a in nv])
+                elif io["kind"] == 0:
+                    new[(x, y, z)][c] = _feq(w, c, val, u)
                 else:
                     sp = float(iolet_weight[z, y, x]) * val
                     uin = [sp * d for d in io["direction"]]
-                    new[(x, y, z)][c] = _feq(w, c, rho, uin) + (1 - omega) * fneq
+                    new[(x, y, z)][c] = _feq(w, c, rho, uin)
     return new
 
 

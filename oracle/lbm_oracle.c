@@ -27,9 +27,15 @@
  *       units (Sec. 2.4 law between extension and pressure).
  *   R5  U_w = U_R + ((Delta r - Delta x)/Delta r)(U_f - U_R), U_R = F U_f,
  *       applied to the full velocity vector of the fluid node (Sec. 2.3).
- *   R6  inlets/outlets (Sec. 3) use the same non-equilibrium extrapolation:
- *       a density iolet prescribes rho and keeps the fluid node's u, a
- *       velocity iolet prescribes u and keeps the fluid node's rho.
+ *   R6  inlets/outlets (Sec. 3, fixed pressure after the cited pressure
+ *       boundary scheme, prescribed velocity at the inlet): the iolet node
+ *       is at equilibrium, without the non-equilibrium part the wall rule
+ *       carries over (zeroth order); a density iolet prescribes rho and
+ *       keeps the fluid node's u (only its component along the iolet's
+ *       inward normal when the caller gives one); a velocity iolet
+ *       prescribes u and keeps the fluid node's rho.  Carrying the
+ *       non-equilibrium part or the tangential velocity over diverges at
+ *       the paper's tau = 0.537 in its R = 50 cylinder.
  *   R7  the update from step n to n+1 uses the drive value at time n.
  *   R8  wall shear stress: sigma = -(1 - 1/(2 tau)) sum_i fneq_i c_i c_i,
  *       traction t = sigma n, WSS = |t - (t.n) n| at fluid sites that have at
@@ -88,6 +94,7 @@ typedef struct {
     int io_kind[MAX_IOLETS];
     double io_a0[MAX_IOLETS], io_amp[MAX_IOLETS], io_period[MAX_IOLETS], io_phase[MAX_IOLETS];
     double io_dir[MAX_IOLETS][3];
+    int io_project[MAX_IOLETS];      /* density iolet with an inward normal */
     int io_set[MAX_IOLETS];
     double *f, *fnew, *fstar;   /* n*Q, array of structures */
     double *rho, *ux, *uy, *uz; /* pre-collision moments of the current step */
@@ -265,6 +272,16 @@ void orc_set_iolet(void *h, int id, int kind, double a0, double amp, double peri
     o->io_dir[id][0] = dir ? dir[0] : 0.0;
     o->io_dir[id][1] = dir ? dir[1] : 0.0;
     o->io_dir[id][2] = dir ? dir[2] : 0.0;
+    o->io_project[id] = 0;
+    if (kind == 0) {
+        /* density iolet: a non-zero direction is its inward normal */
+        double *d = o->io_dir[id];
+        double nn = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        if (nn > 0.0) {
+            for (int a = 0; a < 3; ++a) d[a] /= nn;
+            o->io_project[id] = 1;
+        }
+    }
     o->io_set[id] = 1;
 }
 
@@ -334,10 +351,10 @@ static void step_once(orc_t *o) {
                 out[i] = o->fstar[(size_t)o->index[v] * Q + i];
                 continue;
             }
-            /* Non-equilibrium part of the fluid node, carried to the wall
-             * node (GZS, Sec. 2.3). */
-            double fneq = f[i] - feq_i(i, rho, ux, uy, uz);
             if (lab == 0) {
+                /* Non-equilibrium part of the fluid node, carried to the
+                 * wall node (GZS, Sec. 2.3). */
+                double fneq = f[i] - feq_i(i, rho, ux, uy, uz);
                 if (o->mode == 0) {
                     /* Bounce-back (Sec. 2.4, rigid comparison). */
                     out[i] = o->fstar[(size_t)s * Q + opposite(i)];
@@ -355,15 +372,22 @@ static void step_once(orc_t *o) {
                     out[i] = feq_i(i, rho, Uwx, Uwy, Uwz) + (1.0 - omega) * fneq;
                 }
             } else {
+                /* Iolet (Sec. 3, reading R6): equilibrium at the prescribed
+                 * density and the fluid node's velocity (along the iolet's
+                 * inward normal, if one is set), or at the fluid node's
+                 * density and the prescribed velocity. */
                 int id = lab - 2;
                 double val = drive(o, id, o->t);
-                if (o->io_kind[id] == 0) {
-                    out[i] = feq_i(i, val, ux, uy, uz) + (1.0 - omega) * fneq;
+                if (o->io_kind[id] == 0 && o->io_project[id]) {
+                    const double *nv = o->io_dir[id];
+                    double un = ux * nv[0] + uy * nv[1] + uz * nv[2];
+                    out[i] = feq_i(i, val, un * nv[0], un * nv[1], un * nv[2]);
+                } else if (o->io_kind[id] == 0) {
+                    out[i] = feq_i(i, val, ux, uy, uz);
                 } else {
                     double sp = o->iolet_w[s] * val;
                     out[i] = feq_i(i, rho, sp * o->io_dir[id][0], sp * o->io_dir[id][1],
-                                   sp * o->io_dir[id][2]) +
-                             (1.0 - omega) * fneq;
+                                   sp * o->io_dir[id][2]);
                 }
             }
         }

@@ -455,16 +455,20 @@ __device__ __forceinline__ int remap_xcd(int b, int nblk) {
 }
 
 // Links whose upstream voxel is an elastic wall or an iolet (boundary record
-// j of a site with moments m and post-collision deviations out): for each
-// such link i the value
-//   f_i(x, t+1) = feq_i(rho', U') + (1 - 1/tau) (f_i - feq_i(rho, u))
-//              = feq_i(rho', U') + f*_i - feq_i(rho, u)
-// replaces out[opp(i)], the slot the site pulls for link i at the next step.
-//   elastic wall (Sec. 2.3): rho' = rho, U' = s u,
-//     s = (F + Delta r - 1) / Delta r, Delta r = 1 + Delta E,
+// j of a site with moments m and post-collision deviations out): the value
+// of each such link i replaces out[opp(i)], the slot the site pulls for link
+// i at the next step.
+//   elastic wall (Sec. 2.3): the wall node carries the fluid node's
+//     non-equilibrium part,
+//       f_i(x, t+1) = feq_i(rho, U') + (1 - 1/tau) (f_i - feq_i(rho, u))
+//                  = feq_i(rho, U') + f*_i - feq_i(rho, u),
+//     U' = s u, s = (F + Delta r - 1) / Delta r, Delta r = 1 + Delta E,
 //     Delta E = max(0, (p - P0) / k), p = rho / 3;
-//   density iolet (Sec. 3): rho' = rho_io(t), U' = u;
-//   velocity iolet (Sec. 3): rho' = rho, U' = weight(x) u_io(t) dir.
+//   iolets (Sec. 3): the iolet node is at equilibrium,
+//       f_i(x, t+1) = feq_i(rho', U'),
+//     density iolet rho' = rho_io(t), U' = (u.n) n with n the iolet's unit
+//     inward normal if one is set, else U' = u; velocity iolet rho' = rho,
+//     U' = weight(x) u_io(t) dir.
 // The parts of a boundary record the link rules read.
 template <typename acc>
 struct BRec {
@@ -513,6 +517,13 @@ __device__ __forceinline__ void apply_links(const StepArgs& a, int j, const Mom<
         if (q.kind == LBM_IOLET_DENSITY) {
             idr = vm1;
             ir = v;
+            if (q.pad) {  // the fluid node's velocity along the inward normal only
+                const acc d0 = (acc)q.dir[0], d1 = (acc)q.dir[1], d2 = (acc)q.dir[2];
+                const acc un = m.ux * d0 + m.uy * d1 + m.uz * d2;
+                ix = un * d0;
+                iy = un * d1;
+                iz = un * d2;
+            }
         } else {
             const acc sp = (acc)a.bw[j] * v;
             ix = sp * (acc)q.dir[0];
@@ -541,13 +552,9 @@ __device__ __forceinline__ void apply_links(const StepArgs& a, int j, const Mom<
         const acc t = Bs * ((acc)4.5 * cu[k] * cu[k] - u2), p = (acc)3 * cu[k];
         if (wi) out[o] = oi + w * A * (t + p);
         if (wo) out[i] = oo + w * A * (t - p);
-        if (ii | io) {  // iolet links (rare): general form
-            if (ii)
-                out[o] = oi + heq_one<acc>(i, idr, ir, ix, iy, iz) * sc -
-                         heq_one<acc>(i, m.drho, m.rho, m.ux, m.uy, m.uz) * sc;
-            if (io)
-                out[i] = oo + heq_one<acc>(o, idr, ir, ix, iy, iz) * sc -
-                         heq_one<acc>(o, m.drho, m.rho, m.ux, m.uy, m.uz) * sc;
+        if (ii | io) {  // iolet links (rare): equilibrium at (rho', U')
+            if (ii) out[o] = heq_one<acc>(i, idr, ir, ix, iy, iz) * sc;
+            if (io) out[i] = heq_one<acc>(o, idr, ir, ix, iy, iz) * sc;
         }
     }
 }

@@ -22,9 +22,9 @@ struct InstParams {
 // Per-iolet drive (Sec. 3): value(t) = a0 (1 + amp sin(2 pi t/period + phase)).
 struct IoletParams {
     double a0, amp, inv_period, phase;
-    double dir[3];
+    double dir[3];  // velocity: unit direction; density: inward normal (if project)
     int32_t kind;   // 0 density, 1 velocity
-    int32_t pad;
+    int32_t pad;    // density: 1 keeps only the velocity along dir
 };
 
 // Elastic-wall coefficients of one boundary record (Sec. 2.3, 2.4): with

@@ -950,11 +950,16 @@ int lbm_set_iolet(lbm_ctx* c, int inst, int id, int kind, double a0, double amp,
     q.inv_period = amp != 0.0 ? 1.0 / period : 0.0;
     q.phase = phase;
     q.kind = kind;
+    const double nn = dir ? std::sqrt(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]) : 0.0;
+    if (dir && !std::isfinite(nn)) return fail(c, LBM_EINVAL, "direction must be finite");
     if (kind == LBM_IOLET_VELOCITY) {
         if (!dir) return fail(c, LBM_EINVAL, "velocity iolet needs a direction");
-        const double nn = std::sqrt(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
         if (!(nn > 0.0)) return fail(c, LBM_EINVAL, "direction must be non-zero");
         for (int a = 0; a < 3; ++a) q.dir[a] = dir[comp_src(a, c->axis[inst])];
+    } else if (nn > 0.0) {
+        // density iolet with an inward normal: the velocity along it is kept
+        for (int a = 0; a < 3; ++a) q.dir[a] = dir[comp_src(a, c->axis[inst])] / nn;
+        q.pad = 1;
     }
     s.iolets[id] = q;
     s.iolet_set[id] = 1;
@@ -1098,11 +1103,8 @@ int lbm_read_fields(lbm_ctx* c, int inst, double* rho, double* u, double* wss, f
     if (wss) HIP_TRY(c, hipMemcpyAsync(pw, s_wss, (size_t)n * 8, hipMemcpyDeviceToHost, c->stream));
     if (wall_dr) HIP_TRY(c, hipMemcpyAsync(pd, s_dr, (size_t)n * 4, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
-    for (int64_t k = 0; k < n; ++k)
-        if (!std::isfinite(prho[k]) || !std::isfinite(pu[3 * k]) || !std::isfinite(pu[3 * k + 1]) ||
-            !std::isfinite(pu[3 * k + 2]))
-            return fail(c, LBM_EDIVERGED, "non-finite field at site %lld of instance %d (step %lld)",
-                        (long long)k, inst, (long long)c->step);
+    // outputs are written in canonical order first, then checked, so a
+    // diverged state is still returned in full
     if (ax) {
         const std::vector<int32_t>& m = c->c2i[inst];
         for (int64_t k = 0; k < n; ++k) {
@@ -1114,6 +1116,11 @@ int lbm_read_fields(lbm_ctx* c, int inst, double* rho, double* u, double* wss, f
             if (wall_dr) wall_dr[k] = pd[j];
         }
     }
+    for (int64_t k = 0; k < n; ++k)
+        if (!std::isfinite(prho[k]) || !std::isfinite(pu[3 * k]) || !std::isfinite(pu[3 * k + 1]) ||
+            !std::isfinite(pu[3 * k + 2]))
+            return fail(c, LBM_EDIVERGED, "non-finite field in instance %d (step %lld)", inst,
+                        (long long)c->step);
     return LBM_OK;
 }
 

@@ -100,9 +100,10 @@ def _lattice(c: Case, mode: int, dtype: str, amp: float):
     g = inputs.cylinder(c.R, c.L, with_normals=False)
     lat = lbm.Lattice([g], dtype=dtype, tau=c.tau)
     lat.set_wall(0, mode, F=F_WALL if mode == lbm.ELASTIC else 0.0, P0=1.0 / 3.0, k=[c.k])
-    # density iolets 1 +- amp sin(omega t) on the planes z = 0 and z = L + 1
-    lat.set_iolet(0, 0, lbm.DENSITY, 1.0, amp, float(c.period), 0.0)
-    lat.set_iolet(0, 1, lbm.DENSITY, 1.0, amp, float(c.period), math.pi)
+    # density iolets 1 +- amp sin(omega t) on the planes z = 0 and z = L + 1,
+    # with their inward normals
+    lat.set_iolet(0, 0, lbm.DENSITY, 1.0, amp, float(c.period), 0.0, (0.0, 0.0, 1.0))
+    lat.set_iolet(0, 1, lbm.DENSITY, 1.0, amp, float(c.period), math.pi, (0.0, 0.0, -1.0))
     lat.init_fields(0)
     return g, lat
 

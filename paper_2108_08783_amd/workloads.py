@@ -52,7 +52,9 @@ def _drive(g, u0, period=PERIOD, amp=0.5):
     io = {0: dict(kind=lbm.VELOCITY, a0=u0, amp=amp, period=period,
                   direction=tuple(g.iolets[0]["direction"]))}
     for d in g.iolets[1:]:
-        io[d["id"]] = dict(kind=lbm.DENSITY, a0=1.0)
+        # fixed-density outlets with their inward normal (only the velocity
+        # along it enters the outlet node)
+        io[d["id"]] = dict(kind=lbm.DENSITY, a0=1.0, direction=tuple(d["direction"]))
     return io
 
 

@@ -93,7 +93,7 @@ def tube_problem(R, L, *, seed=0, mode=lbm.ELASTIC, pulsatile=True, period=400.0
     k = float(inputs.log_uniform(rng, 1e-3, 1e-1))
     io = {0: dict(kind=lbm.VELOCITY, a0=0.02, amp=0.5 if pulsatile else 0.0, period=period,
                   direction=(0.0, 0.0, 1.0)),
-          1: dict(kind=lbm.DENSITY, a0=1.0)}
+          1: dict(kind=lbm.DENSITY, a0=1.0, direction=(0.0, 0.0, -1.0))}
     return Problem(geo=g, tau=0.8, mode=mode, F=F, P0=1.0 / 3.0, k=[k], iolets=io)
 
 
@@ -102,7 +102,8 @@ def poiseuille_problem(mode, seed=0):
     1.001 / outlet 0.999, rho0 = 1 + U(-1e-6, 1e-6)."""
     g = inputs.cylinder(8, 64)
     rho0 = inputs.density_perturbation(g.n_fluid, seed)
-    io = {0: dict(kind=lbm.DENSITY, a0=1.001), 1: dict(kind=lbm.DENSITY, a0=0.999)}
+    io = {0: dict(kind=lbm.DENSITY, a0=1.001, direction=(0.0, 0.0, 1.0)),
+          1: dict(kind=lbm.DENSITY, a0=0.999, direction=(0.0, 0.0, -1.0))}
     return Problem(geo=g, tau=0.8, mode=mode, F=0.85, P0=0.999 / 3.0, k=[1e-2], iolets=io,
                    rho0=rho0)
 

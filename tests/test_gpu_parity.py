@@ -330,7 +330,7 @@ def _tree_problem(scale, seed=3):
     inlet_dir = g.iolets[0]["direction"]
     io = {0: dict(kind=lbm.VELOCITY, a0=0.02, amp=0.5, period=400.0, direction=inlet_dir)}
     for d in g.iolets[1:]:
-        io[d["id"]] = dict(kind=lbm.DENSITY, a0=1.0)
+        io[d["id"]] = dict(kind=lbm.DENSITY, a0=1.0, direction=tuple(d["direction"]))
     return H.Problem(geo=g, tau=0.8, mode=lbm.ELASTIC, F=0.5, P0=1.0 / 3.0, k=k, iolets=io)
 
 
@@ -355,7 +355,7 @@ def test_batch_of_tubes_and_bifurcations():
         io = {0: dict(kind=lbm.VELOCITY, a0=q["u0"], amp=0.5, period=300.0,
                       direction=g.iolets[0]["direction"])}
         for d in g.iolets[1:]:
-            io[d["id"]] = dict(kind=lbm.DENSITY, a0=1.0)
+            io[d["id"]] = dict(kind=lbm.DENSITY, a0=1.0, direction=tuple(d["direction"]))
         probs.append(H.Problem(geo=g, tau=0.8, mode=lbm.ELASTIC, F=0.5, P0=1.0 / 3.0,
                                k=[q["k"]] * g.n_seg, iolets=io))
     lat = H.make_lattice(probs, "f32")

@@ -1,23 +1,28 @@
-"""The paper's verification cylinder (Sec. 2.4, R = 50 lattice spacings,
-alpha = 3, run at tau = 0.8 as the same dimensionless problem): after three
-periods the rigid run follows the rigid Womersley solution, and the elastic
-run follows the elastic-tube shape with M from the Sec. 2.3 relation at the
-paper's F = 0.85 better than the rigid shape, within the paper's error
-level."""
+"""The paper's verification cylinder at its own lattice parameters (Sec. 2.4,
+Table A1: R = 50 lattice spacings, tau = 0.537, alpha = 3, 5.2M sites):
+after three periods the rigid run follows the rigid Womersley solution,
+and the elastic run follows the elastic-tube shape with M from the Sec. 2.3
+relation at the paper's F = 0.85, better than the rigid shape and, at the
+median phase, within the paper's error level of 10 %."""
 import pytest
 
 pytestmark = pytest.mark.gpu
 
 
-def test_womersley_rigid_and_elastic_shapes():
+def test_womersley_rigid_and_elastic_shapes_at_the_papers_tau():
     from paper_2108_08783_amd import lbm, verification
-    rigid = verification.womersley(50, lbm.BOUNCEBACK, tau=0.8, log=print)
-    elastic = verification.womersley(50, lbm.ELASTIC, tau=0.8, log=print)
+    rigid = verification.womersley(50, lbm.BOUNCEBACK, log=print)
+    elastic = verification.womersley(50, lbm.ELASTIC, log=print)
+    assert abs(rigid["tau"] - 0.537) < 5e-4 and abs(elastic["tau"] - 0.537) < 5e-4
     # rigid: measured-gradient Womersley solution and the fitted rigid shape
     assert max(p["err_rel_amplitude"] for p in rigid["phases"]) < 0.03
     assert rigid["shape_fits"]["rigid_model"]["err_max_rel_amplitude"] < 0.03
-    # elastic: the elastic shape fits, and fits better than the rigid one
+    # elastic: the elastic shape fits to the paper's level, and better than
+    # the rigid one
     fe = elastic["shape_fits"]["elastic_model"]["err_max_rel_amplitude"]
     fr = elastic["shape_fits"]["rigid_model"]["err_max_rel_amplitude"]
-    print({"elastic_model": fe, "rigid_model": fr})
-    assert fe < 0.13 and fe < 0.75 * fr
+    per_phase = sorted(elastic["shape_fits"]["elastic_model"]["phase_err_rel_amplitude"])
+    print({"elastic_model": fe, "rigid_model": fr, "elastic_model_phases": per_phase}, flush=True)
+    # the paper's level (under 10 %) at the median phase; the worst phase,
+    # where the velocities are smallest, within 12 %
+    assert per_phase[len(per_phase) // 2] < 0.10 and fe < 0.12 and fe < 0.75 * fr

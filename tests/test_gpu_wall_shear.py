@@ -1,8 +1,11 @@
-"""Rigid against elastic wall shear stress on a half-scale tree (about
-0.94M sites, drive period 4000 steps): run to a periodic state with each wall
-rule, the elastic walls (one global F, and one F per vessel from the
-Sec. 2.3 relation) must give a lower wall shear stress than bounce-back at
-nearly every wall site, as in the paper's pointwise comparison (Sec. 3, Fig. 11)."""
+"""Rigid against elastic wall shear stress on the 7.5M-site Murray tree
+(drive period 4000 steps): run to a periodic state with each wall rule, the
+elastic walls (one global F, and one F per vessel from the Sec. 2.3
+relation, 0.70-0.88 here) must give a lower wall shear stress than
+bounce-back at nearly every wall site, as in the paper's pointwise
+comparison (Sec. 3, Fig. 11).  (On the half-scale tree the relation gives
+F up to 0.97, nearly free slip, and the leaf stubs there do not reach a
+periodic state with outlets that keep only the normal velocity.)"""
 import pytest
 
 pytestmark = pytest.mark.gpu
@@ -10,7 +13,7 @@ pytestmark = pytest.mark.gpu
 
 def test_elastic_walls_lower_the_wall_shear_stress():
     from paper_2108_08783_amd import wall_shear, workloads
-    wl = workloads.tree(scale=0.5)
+    wl = workloads.tree()
     r = wall_shear.study(wl, "f32", phases=8, max_cycles=20)
     for run in r["runs"].values():
         assert run["cycles"] > 0

@@ -159,12 +159,15 @@ def test_one_step_matches_brute_force(mode, seed):
     k = [0.02, 0.005, 1e-3]
     F, P0 = 0.6, 0.331
     o.set_wall(mode, F=F, P0=P0, k=k)
+    # the density iolet's inward normal: given (seeds 1, 2: only the velocity
+    # along it is kept) or none (seed 3: the whole velocity)
     iol = {0: dict(kind=0, a0=1.002, amp=0.3, period=17.0, phase=0.4,
-                   direction=geo.iolets[0]["direction"]),
+                   direction=geo.iolets[0]["direction"] if seed != 3 else None),
            1: dict(kind=1, a0=0.03, amp=0.5, period=11.0, phase=-1.0,
                    direction=geo.iolets[1]["direction"])}
     for i, p in iol.items():
-        o.set_iolet(i, p["kind"], p["a0"], p["amp"], p["period"], p["phase"], p["direction"])
+        o.set_iolet(i, p["kind"], p["a0"], p["amp"], p["period"], p["phase"],
+                    p["direction"] if p["direction"] is not None else (0.0, 0.0, 0.0))
     o.init_fields()
     o.step(5)                       # advance the drive clock
     c, w = oracle.velocity_set()
