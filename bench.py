@@ -121,7 +121,10 @@ def copy_probe(gib=1.0, reps=20):
 
 def roof_window(steps):
     """Launches in a roofline window: at least ROOF_MIN_LAUNCHES, a multiple
-    of 128 (whole graph replays)."""
+    of 128 (whole graph replays); 0 when ROOF_MIN_LAUNCHES is 0 (profiling
+    runs that want only the timed steps)."""
+    if ROOF_MIN_LAUNCHES == 0:
+        return 0
     n = max(ROOF_MIN_LAUNCHES, steps)
     return (n + 127) // 128 * 128
 
@@ -151,7 +154,7 @@ def gpu_run(wl, dtype, steps, warmup, bounceback=False, tune=True, launch=None, 
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     win = roof_window(steps)
-    roof_ms = lat.time_steps(win)       # graph replays, HIP events
+    roof_ms = lat.time_steps(win) if win else ms   # graph replays, HIP events
     info = lat.info()
     for k in range(len(wl.geoms)):
         lat.read_fields(k, wss=False, wall_dr=False)  # raises if diverged
@@ -161,7 +164,7 @@ def gpu_run(wl, dtype, steps, warmup, bounceback=False, tune=True, launch=None, 
           f"roofline window {win} launches {roof_ms:.1f} ms", file=sys.stderr, flush=True)
     return dict(n=n, wall_s=t1 - t0, event_ms=ms, info=info,
                 mlups=n * steps / (t1 - t0) / 1e6,
-                launch_us=roof_ms * 1e3 / win, window=win)
+                launch_us=roof_ms * 1e3 / (win or steps), window=win or steps)
 
 
 def summary(r, dtype, with_traffic=False):
@@ -170,6 +173,7 @@ def summary(r, dtype, with_traffic=False):
                roofline_frac=round(ach / PEAK_GBS, 4), achieved_gbs=round(ach, 1),
                window_launches=r["window"],
                index_bits=r["info"]["index_bits"], block=r["info"]["block_size"],
+               xcd_remap=r["info"]["xcd_remap"], nontemporal=r["info"]["nontemporal"],
                fused=r["info"]["boundary_fused"], boundary_sites=r["info"]["n_boundary"])
     if with_traffic:
         out["traffic"] = traffic_from_profiles(dtype, with_traffic)
@@ -221,6 +225,7 @@ def cpu_baseline(wl, target_s=15.0):
 
 
 def main():
+    global ROOF_MIN_LAUNCHES
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=4096)
@@ -234,7 +239,11 @@ def main():
                     help="JSON launch configuration instead of autotuning")
     ap.add_argument("--probe-copy", action="store_true",
                     help="only run the plain-copy bandwidth probe")
+    ap.add_argument("--window", type=int, default=2048,
+                    help="minimum launches of the roofline window (0: use the timed steps; "
+                         "for profiling runs)")
     args = ap.parse_args()
+    ROOF_MIN_LAUNCHES = max(0, args.window)
     if args.gpus != 1:
         print(f"bench.py: the library runs on one GPU only (got --gpus {args.gpus}); "
               "a batch would shard by instance and one large domain by site ranges with a "

@@ -116,31 +116,6 @@ def random_labels(shape, rng: np.random.Generator, p_fluid=0.7, n_iolets=2) -> G
     return geo
 
 
-def separate_iolets(geo: Geometry) -> Geometry:
-    """Turns iolet voxels into wall voxels until no fluid voxel has upstream
-    neighbours in two different iolets (the GPU library allows one iolet per
-    site).  Deterministic: the higher id loses."""
-    lab = geo.labels
-    nz, ny, nx = lab.shape
-    offs = [(dx, dy, dz) for dx in (-1, 0, 1) for dy in (-1, 0, 1) for dz in (-1, 0, 1)
-            if 0 < dx * dx + dy * dy + dz * dz <= 2]
-    changed = True
-    while changed:
-        changed = False
-        for z, y, x in zip(*np.nonzero(lab == FLUID)):
-            seen = {}
-            for dx, dy, dz in offs:
-                v = int(lab[z - dz, y - dy, x - dx])
-                if v >= IOLET0:
-                    seen.setdefault(v, []).append((z - dz, y - dy, x - dx))
-            if len(seen) > 1:
-                for v in sorted(seen)[1:]:
-                    for zz, yy, xx in seen[v]:
-                        lab[zz, yy, xx] = WALL
-                changed = True
-    return geo
-
-
 def _unit_rows(rng, n):
     v = rng.normal(size=(n, 3))
     return v / np.linalg.norm(v, axis=1, keepdims=True)
@@ -318,7 +293,7 @@ _OFFS18 = [(dx, dy, dz) for dx in (-1, 0, 1) for dy in (-1, 0, 1) for dz in (-1,
 
 
 def _resolve_iolet_conflicts(lab):
-    """Vectorised form of separate_iolets: a fluid voxel whose upstream
+    """A fluid voxel whose upstream
     neighbours lie in two different iolets loses the higher-id iolet voxels
     (they become wall).  Only the neighbourhoods of iolet voxels are
     examined."""

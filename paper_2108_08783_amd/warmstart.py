@@ -523,18 +523,31 @@ def instance_prior(geo, frame: SiteFrame, params, phase, nu=0.1) -> Prior:
                          amp=io["amp"], period=io["period"])
 
 
+# Outside the training range: "gate" applies no correction at a site with
+# any feature outside it; "clamp" moves every feature into the range first
+# (the network is then used everywhere, saturating at the range boundary).
+OUT_OF_RANGE = "gate"
+
+
 def predict(net, geo, frame: SiteFrame, params, phase, nu=0.1, chunk=1 << 20, use_net=True,
-            prior: Optional[Prior] = None):
+            prior: Optional[Prior] = None, out_of_range: Optional[str] = None):
     """(rho, u) of every site of one instance: the network prior plus the
-    network's correction (clipped to the trust region, only at sites whose
-    features lie inside the training range)."""
+    network's correction (clipped to the trust region; sites with features
+    outside the training range handled by `out_of_range`, default
+    OUT_OF_RANGE)."""
     import torch
     u0 = params.iolets[0]["a0"]
     pr = prior if prior is not None else instance_prior(geo, frame, params, phase, nu)
     Y = pr.Y.copy()
     if use_net:
         X = features(frame, params.k, u0, phase, pr)
-        ok = in_range(X, getattr(net, "feature_range", None))
+        fr = getattr(net, "feature_range", None)
+        mode = out_of_range or OUT_OF_RANGE
+        if mode == "clamp" and fr is not None:
+            X = np.clip(X, fr[0].astype(np.float32), fr[1].astype(np.float32))
+            ok = np.ones(X.shape[0], bool)
+        else:
+            ok = in_range(X, fr)
         for s in range(0, X.shape[0], chunk):
             xb = net.to_bf16(torch.tensor(X[s:s + chunk], device="cuda"))
             # trust region: the correction to the prior is at most one output
@@ -747,7 +760,12 @@ def main(argv=None):
     ap.add_argument("--out", default=None, help="write the full result (JSON)")
     ap.add_argument("--merge", nargs="+", default=None,
                     help="only combine the per-instance results of earlier --out files")
+    ap.add_argument("--out-of-range", choices=("gate", "clamp"), default="gate",
+                    help="sites with features outside the training range: no correction "
+                         "(gate) or features clamped into the range (clamp)")
     a = ap.parse_args(argv)
+    global OUT_OF_RANGE
+    OUT_OF_RANGE = a.out_of_range
     if a.merge:
         runs = [json.load(open(f)) for f in a.merge]
         results = {}

@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 from paper_2108_08783_amd import inputs
+from tests import helpers as H
 from paper_2108_08783_amd import lbm
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -63,7 +64,7 @@ def _index_grid(labels):
 @pytest.mark.parametrize("mode", [lbm.BOUNCEBACK, lbm.ELASTIC])
 def test_pull_table_invariants(mode):
     rng = np.random.default_rng(5)
-    geos = [inputs.separate_iolets(inputs.random_labels((7, 8, 9), rng)), inputs.cylinder(5, 9)]
+    geos = [H.one_iolet_per_site(inputs.random_labels((7, 8, 9), rng)), inputs.cylinder(5, 9)]
     p = lbm.lbm_plan_export(geos, wall_modes=[mode, mode])
     nbr = p["nbr"]
     N = p["n_sites"]
@@ -149,7 +150,7 @@ def test_compressed_addressing_reproduces_the_table(mode):
     many multi-run rows, convex tubes none."""
     rng = np.random.default_rng(7 + mode)
     for _ in range(4):
-        g = inputs.separate_iolets(inputs.random_labels((12, 9, 10), rng, p_fluid=0.7))
+        g = H.one_iolet_per_site(inputs.random_labels((12, 9, 10), rng, p_fluid=0.7))
         st = lbm.lbm_plan_compressed([g], [mode])
         n = lbm.lbm_plan_export([g], wall_modes=[mode], tables=False)["n_sites"]
         assert st["records"] == (max(256, (n + 255) // 256 * 256)) // 64
@@ -187,3 +188,37 @@ def test_fast_axis_override(monkeypatch):
     monkeypatch.setenv("LBM_FAST_AXIS", "w")
     with pytest.raises(lbm.LbmError):
         lbm.lbm_fast_axis([tube])
+
+
+def test_two_iolets_at_one_site_are_rejected_by_the_library_only():
+    """The library's one-iolet-per-site limit (reading 11): unrestricted
+    random boxes that have a fluid site next to two different iolets are
+    rejected by the host build with a message naming the limit, while the
+    oracle steps them; restricted, the same boxes are accepted."""
+    import oracle
+    rng = np.random.default_rng(5)
+    found = 0
+    for _ in range(20):
+        g = inputs.random_labels((8, 9, 10), rng)
+        lab = g.labels
+        fl = np.argwhere(lab == inputs.FLUID)
+        two = False
+        for z, y, x in fl:
+            ids = {int(lab[z - dz, y - dy, x - dx]) for dx in (-1, 0, 1) for dy in (-1, 0, 1)
+                   for dz in (-1, 0, 1) if 0 < dx * dx + dy * dy + dz * dz <= 2
+                   and lab[z - dz, y - dy, x - dx] >= inputs.IOLET0}
+            two |= len(ids) > 1
+        if not two:
+            continue
+        found += 1
+        with pytest.raises(lbm.LbmError, match="iolet"):
+            lbm.lbm_plan_export([g], tables=False)
+        o = oracle.Oracle(g.labels, 0.8)
+        o.set_wall(0)
+        for i in range(2):
+            o.set_iolet(i, 0, 1.0 + 0.001 * i)
+        o.init_fields()
+        o.step(5)
+        assert np.isfinite(o.read()[1]).all()
+        lbm.lbm_plan_export([H.one_iolet_per_site(g)], tables=False)
+    assert found >= 3
