@@ -37,6 +37,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import os
 import time
 from typing import List, Optional, Sequence
 
@@ -609,6 +610,12 @@ def compare_starts(net, wl: workloads.Workload, dtype="f32", tol=1e-3, max_cycle
 
 # ------------------------------------------------------------- experiment --
 MODES = ("cold", "prior", "warm")
+
+# A network trained by `experiment()` with the default settings (256 sweep
+# instances, seeds 1000-1255, 8 phases, 2048 sites per instance and phase,
+# 30 epochs): python -m paper_2108_08783_amd.warmstart --test-sweep 16
+# --test-trees 4 --save-net <file>, parameters stored as float32.
+NET_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "warmstart_net.npz")
 
 
 def save_net_file(path, net):

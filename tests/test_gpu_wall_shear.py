@@ -21,3 +21,60 @@ def test_elastic_walls_lower_the_wall_shear_stress():
         for phase in ("peak", "time_mean"):
             s = r[key][phase]
             assert s["frac_lower"] > 0.9 and s["median_ratio"] < 0.95, (key, phase, s)
+
+
+def test_wall_shear_comparison_matches_the_oracle():
+    """The rigid-against-elastic comparison (Sec. 3, Fig. 11) computed from
+    the GPU's wall shear stress and from the FP64 oracle's, on the
+    quarter-scale tree (105k sites, drive period 400 steps): both start
+    from rest, run three periods with bounce-back and with elastic walls
+    (F = 0.5), then sample the wall shear stress at every wall site at 8
+    phases of a fourth.  Site by site the GPU's samples match the oracle's
+    to 1e-4 of their maximum, and the comparison statistics (fraction of
+    sites lower, median ratio, slope, correlation, at peak flow and time
+    averaged) agree to 1e-4."""
+    import dataclasses
+    import numpy as np
+    import oracle
+    from paper_2108_08783_amd import lbm, wall_shear, workloads
+    wl = workloads.tree(scale=0.25, period=400.0)
+    g, base = wl.geoms[0], wl.params[0]
+    sites = wall_shear.wall_sites(g)
+    period, phases, cycles = 400, 8, 3
+    W, Wo = {}, {}
+    for name, mode in (("rigid", lbm.BOUNCEBACK), ("elastic", lbm.ELASTIC)):
+        p = dataclasses.replace(base, mode=mode)
+        lat = lbm.Lattice(wl.geoms, dtype="f32", tau=wl.tau)
+        workloads.apply(lat, dataclasses.replace(wl, params=[p]))
+        lat.step(cycles * period)
+        W[name], _ = wall_shear.sample_cycle(lat, sites, period, phases)
+        lat.close()
+        o = oracle.Oracle(g.labels, wl.tau, segment=g.segment, normal=g.normal,
+                          iolet_weight=g.iolet_weight)
+        o.set_wall(mode, F=p.F, P0=p.P0, k=p.k)
+        for i, q in p.iolets.items():
+            o.set_iolet(i, q["kind"], q["a0"], q.get("amp", 0.0), q.get("period", 1.0),
+                        q.get("phase", 0.0), q.get("direction", (0.0, 0.0, 0.0)))
+        o.init_fields()
+        o.step(cycles * period)
+        Wo[name] = np.zeros_like(W[name])
+        for j in range(phases):
+            Wo[name][j] = o.read()[2][sites]
+            o.step(period // phases)
+        err = np.abs(W[name] - Wo[name]).max() / np.abs(Wo[name]).max()
+        print(f"wall shear {name}: {len(sites)} wall sites, rel Linf {err:.2e}", flush=True)
+        assert err <= 1e-4, name
+    peak = phases // 4
+    stats = {}
+    for src, w in (("gpu", W), ("oracle", Wo)):
+        tawss = {k: v.mean(axis=0) for k, v in w.items()}
+        floor = 1e-3 * float(tawss["rigid"].max())
+        stats[src] = dict(peak=wall_shear.compare(w["elastic"][peak], w["rigid"][peak], floor),
+                          time_mean=wall_shear.compare(tawss["elastic"], tawss["rigid"], floor))
+    print("wall shear comparison", stats, flush=True)
+    for phase in ("peak", "time_mean"):
+        a, b = stats["gpu"][phase], stats["oracle"][phase]
+        assert abs(a["sites"] - b["sites"]) <= 2
+        for key in ("frac_lower", "median_ratio", "slope", "corr"):
+            assert abs(a[key] - b[key]) <= 1e-4 * max(1.0, abs(b[key])), (phase, key, a[key], b[key])
+    assert stats["oracle"]["peak"]["frac_lower"] > 0.5
