@@ -348,7 +348,7 @@ def main():
         metric=METRIC, value=round(main_run["mlups"], 1), unit="MLUPS", n_gpus=1,
         steps=args.steps, warmup=args.warmup,
         ms_per_step=round(main_run["wall_s"] * 1e3 / args.steps, 5),
-        higher_is_better=True, scaling="weak", vs_baseline=None, dtype=dtype,
+        higher_is_better=True, scaling="strong", vs_baseline=None, dtype=dtype,
         data="synthetic",
         config=dict(workload=WORKLOADS[args.workload][1],
                     sites=n, boundary_sites=info["n_boundary"], storage=dtype,

@@ -119,7 +119,7 @@ typedef struct {
     int32_t index_bits;      /* 0 compressed addressing, 16/32 offset table  */
     int32_t block_size;      /* threads per block of the update kernel       */
     int32_t use_graph;       /* 1: lbm_step replays captured HIP graphs      */
-    int32_t xcd_remap;       /* 1: block -> XCD-contiguous site ranges       */
+    int32_t xcd_remap;       /* block -> XCD order (see lbm_set_launch)      */
     int32_t nontemporal;     /* bit 0 stores, bit 1 loads bypass the caches  */
     int32_t boundary_fused;  /* 1: boundary links applied inside the update   */
     int32_t sites_per_lane;  /* sites updated per lane in the update blocks   */
@@ -324,7 +324,10 @@ int lbm_instance_sites(const lbm_ctx* ctx, int inst, int64_t* n);
  * 512, 1024}; index_bits: 0 for compressed addressing (interior sites derive
  * their offsets from per-row offsets shared along runs of interior sites),
  * 16 or 32 for a per-site offset table (16 only if every neighbour offset
- * fits, else LBM_EINVAL); use_graph, xcd_remap booleans; nontemporal bit 0:
+ * fits, else LBM_EINVAL); use_graph boolean; xcd_remap: 0 blocks in launch
+ * order (the hardware deals them round-robin to the 8 XCDs), 1 one
+ * contiguous site range per XCD, g = 2..4096 (a power of two) runs of g
+ * neighbouring blocks per XCD, advancing together; nontemporal bit 0:
  * population stores bypass the caches, bit 1: population loads do;
  * boundary_fused 1: sites with elastic-wall or iolet links are updated by
  * the same blocks as all other sites, which apply the link rules in place;

@@ -454,6 +454,23 @@ __device__ __forceinline__ int remap_xcd(int b, int nblk) {
     return j * per + (j < rem ? j : rem) + k;
 }
 
+// The same in chunks of g consecutive blocks (g a power of two): the k-th
+// block that XCD j receives runs block ((k / g) * 8 + j) * g + k % g, so
+// each XCD works through its own run of g neighbouring blocks at a time and
+// the eight runs advance together through the site range (the work of a
+// geometry whose cost varies along the site order stays balanced between
+// the XCDs).  Blocks beyond the last whole round of 8 g keep their index.
+__device__ __forceinline__ int remap_xcd_chunk(int b, int nblk, int g) {
+    const int full = nblk / (8 * g) * (8 * g);
+    if (b >= full) return b;
+    const int j = b & 7, k = b >> 3;
+    return ((k / g) * 8 + j) * g + (k & (g - 1));
+}
+
+__device__ __forceinline__ int remap_block(int b, int nblk, int mode) {
+    return mode == 0 ? b : mode == 1 ? remap_xcd(b, nblk) : remap_xcd_chunk(b, nblk, mode);
+}
+
 // Links whose upstream voxel is an elastic wall or an iolet (boundary record
 // j of a site with moments m and post-collision deviations out): the value
 // of each such link i replaces out[opp(i)], the slot the site pulls for link
@@ -648,7 +665,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(step_waves
 void k_step(StepArgs a) {
     const int b = blockIdx.x;
     if (b < a.n_int_blocks) {
-        const int lb = a.xcd_remap ? remap_xcd(b, a.n_int_blocks) : b;
+        const int lb = remap_block(b, a.n_int_blocks, a.xcd_remap);
         const int x = lb * (int)blockDim.x + (int)threadIdx.x;
         if (x < a.n) update_site<DT, ADDR, true, SMALL, NTL>(a, x, false);
     } else {

@@ -49,7 +49,7 @@ struct StepArgs {
     int32_t n;              // fluid sites
     int32_t n_int_blocks;   // blocks of the interior part
     int32_t nb;             // boundary sites
-    int32_t xcd_remap;
+    int32_t xcd_remap;      // 0 off, 1 one site range per XCD, g >= 2: runs of g blocks
     int32_t nontemporal;
     int32_t clock_in;       // clock slot read this step; the other is written
     int32_t fused;          // 1: boundary links applied inside the update blocks

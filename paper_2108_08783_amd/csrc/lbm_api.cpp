@@ -1319,13 +1319,16 @@ int lbm_set_launch(lbm_ctx* c, int block_size, int index_bits, int use_graph, in
         return fail(c, LBM_EINVAL, "index_bits must be 0 (compressed), 16 or 32");
     if (sites_per_lane != -1 && sites_per_lane != 1)
         return fail(c, LBM_EINVAL, "sites_per_lane must be 1");
+    if (xcd_remap != -1 && xcd_remap != 0 && xcd_remap != 1 &&
+        (xcd_remap < 2 || xcd_remap > 4096 || (xcd_remap & (xcd_remap - 1))))
+        return fail(c, LBM_EINVAL, "xcd_remap must be 0, 1 or a power of two up to 4096");
     if (index_bits == 16 && !c->have16)
         return fail(c, LBM_EINVAL, "a neighbour offset exceeds the 16-bit range (max %lld)",
                     (long long)c->plan.max_abs_offset);
     if (block_size != -1) c->block = block_size;
     if (index_bits != -1) c->ibits = index_bits;
     if (use_graph != -1) c->use_graph = use_graph ? 1 : 0;
-    if (xcd_remap != -1) c->xcd = xcd_remap ? 1 : 0;
+    if (xcd_remap != -1) c->xcd = xcd_remap;
     if (nontemporal != -1) c->nt = nontemporal & 3;
     if (boundary_fused != -1) c->fused = boundary_fused ? 1 : 0;
     if (sites_per_lane != -1) c->spt = sites_per_lane;
@@ -1370,29 +1373,35 @@ int lbm_autotune(lbm_ctx* c, int steps_per_trial, double* best_rate) {
     const int ibits_list[] = {0, 16, 32};
     // pass 1: every configuration once (non-temporal loads are left out:
     // the gathers share cache lines between neighbouring wavefronts)
+    // (block orders: launch order, one range per XCD, and for compressed
+    // addressing in the fused mode also runs of 4 and 16 blocks per XCD)
     std::vector<std::pair<double, TuneVal>> cand;
+    std::vector<TuneVal> trials;
     for (int ib : ibits_list) {
         if (ib == 16 && !c->have16) continue;
-        for (int fu = 0; fu < 2 && !rc; ++fu)
+        for (int fu = 0; fu < 2; ++fu)
             for (int bs : blocks)
-                for (int xr = 0; xr < 2 && !rc; ++xr)
-                    for (int ntv = 0; ntv < 2 && !rc; ++ntv) {
-                        rc = lbm_set_launch(c, bs, ib, -1, xr, ntv, fu, 1);
-                        if (rc) break;
-                        double ms = 0;
-                        rc = run_steps(c, 2);  // warm-up (and graph build)
-                        rc = rc ? rc : lbm_time_steps(c, steps_per_trial, &ms);
-                        if (rc) break;
-                        cand.push_back({ms, TuneVal{bs, ib, xr, ntv, fu, 1}});
-                    }
+                for (int xr : {0, 1, 4, 16}) {
+                    if (xr > 1 && (ib != 0 || !fu)) continue;
+                    for (int ntv = 0; ntv < 2; ++ntv) trials.push_back(TuneVal{bs, ib, xr, ntv, fu, 1});
+                }
+    }
+    for (const TuneVal& v : trials) {
+        rc = lbm_set_launch(c, v.block, v.ibits, -1, v.xcd, v.nt, v.fused, v.spt);
         if (rc) break;
+        double ms = 0;
+        rc = run_steps(c, 2);  // warm-up (and graph build)
+        rc = rc ? rc : lbm_time_steps(c, steps_per_trial, &ms);
+        if (rc) break;
+        cand.push_back({ms, v});
     }
     // pass 2: the six fastest again, three times each with twice the steps
     // (single short trials are noisy: clocks and cache contents vary).  The
-    // XCD order moves fewer bytes (neighbouring wavefronts share lines in
-    // one L2; the tree in FP32 reads 1.08 instead of 1.19 times the
-    // algorithmic bytes), so it is kept unless the other order is more than
-    // 2 % faster
+    // block orders that keep neighbouring blocks on one XCD move fewer
+    // bytes (neighbouring wavefronts share lines in one L2; the tree in FP32
+    // reads 1.08 instead of 1.19 times the algorithmic bytes with one range
+    // per XCD), so they are kept unless the launch order is more than 2 %
+    // faster
     if (!rc) {
         std::sort(cand.begin(), cand.end(),
                   [](const std::pair<double, TuneVal>& a, const std::pair<double, TuneVal>& b) {

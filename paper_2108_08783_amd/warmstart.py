@@ -7,18 +7,23 @@ after which the ordinary update runs unchanged.  The zero-velocity start is
 the fallback and the reference: both starts must converge to the same periodic
 state, and the figure of merit is the number of cardiac cycles needed.
 
-Features (16 per site, host-side, from the generator's segment list):
+Features (16 per site, host-side, from the generator's segment list), in
+one of two sets that differ in slots 1, 2 and 7-9:
   0  (r(t) - |x - q|) / r(t): wall distance relative to the local radius
-  1  r(t) / 24: local radius
-  2  r(t) / r_inlet: radius relative to the inlet
+  1  absolute: r(t) / 24, the local radius;
+     scale_free: r(t) / r_ref, the radius relative to the parent segment's
+     end radius (the segment's own start radius for the root), about 0.79
+     at every Murray branching
+  2  absolute: r(t) / r_inlet;
+     scale_free: the generation of the owning segment (0 for the root)
   3  t: position along the owning segment (0 at its start)
   4  path position: distance from the inlet along the tree over the
      (mean) inlet-to-outlet path length through the segment
   5  the prior's density output (below)
   6  downstream path length over r_inlet, scaled by 1/40
-  7-9 generation one-hot (0, 1, deeper); the deeper slot starts at zero
-     weight, so generations absent from the training data contribute
-     nothing
+  7-9 absolute: generation one-hot (0, 1, deeper); the deeper slot starts
+     at zero weight, so generations absent from the training data
+     contribute nothing; scale_free: zero
   10 the prior's axial velocity over u0
   11 the prior's slip factor at the local mean pressure
   12 log10(k) + 2: wall stiffness of the segment
@@ -31,7 +36,14 @@ slip-Poiseuille mean flow and, at the drive frequency, a transmission line
 per segment with the slip Womersley impedance and the lattice's
 compressibility.  The correction is applied only at sites whose features
 all lie inside the range seen in training (with a 5 % margin); elsewhere
-the start is the prior.
+the start is the prior.  The training instances (tubes and single
+bifurcations, radii 6-24) hold generations 0 and 1 only.  With the absolute
+set the held-out Murray trees (radii up to 40, generations to 4) fall
+outside that range at every site, so the trees start from the prior; the
+scale-free set puts about 70 % of their sites inside it (the generation
+gate keeps generations 2 and deeper out), and the correction learned on
+single bifurcations then makes the trees' starts worse than the prior.
+The absolute set is the default.
 """
 from __future__ import annotations
 
@@ -54,6 +66,7 @@ N_FEAT, N_OUT = 16, 4
 @dataclasses.dataclass
 class SiteFrame:
     static: np.ndarray   # [n, 12] float32, features 0..11
+    r: np.ndarray        # [n] local radius r(t) of the owning segment
     seg: np.ndarray      # [n] owning segment
     axis: np.ndarray     # [n, 3]
     radial: np.ndarray   # [n, 3]
@@ -93,13 +106,22 @@ def _path_lengths(segs):
     return start, lengths, total, rem
 
 
-def site_frames(geo: inputs.Geometry) -> SiteFrame:
+FEATURE_SETS = ("absolute", "scale_free")
+
+
+def site_frames(geo: inputs.Geometry, feature_set: str = "absolute") -> SiteFrame:
+    if feature_set not in FEATURE_SETS:
+        raise ValueError(f"feature_set must be one of {FEATURE_SETS}")
     segs = geo.segments
     assert segs, "geometry needs its segment list"
     zz, yy, xx = np.nonzero(geo.labels == inputs.FLUID)
     pos = np.stack([xx, yy, zz], 1).astype(np.float64)
     n_id = max(s.sid for s in segs) + 1
     # per-segment constants, gathered per site (segments are few)
+    parent, _ = _topology(segs)
+    RREF = np.ones(n_id)
+    for j, sg in enumerate(segs):
+        RREF[sg.sid] = segs[parent[j]].r1 if parent[j] >= 0 else sg.r0
     P0 = np.zeros((n_id, 3))
     A = np.zeros((n_id, 3))
     Ls = np.ones(n_id)
@@ -147,15 +169,19 @@ def site_frames(geo: inputs.Geometry) -> SiteFrame:
     r_in = segs[0].r0
     static = np.zeros((n, 12), np.float32)
     static[:, 0] = np.clip((r - dist) / r, -0.5, 1.0)
-    static[:, 1] = r / 24.0
-    static[:, 2] = r / r_in
+    if feature_set == "scale_free":
+        static[:, 1] = r / RREF[sid]
+        static[:, 2] = gen
+    else:
+        static[:, 1] = r / 24.0
+        static[:, 2] = r / r_in
+        static[:, 7] = gen == 0
+        static[:, 8] = gen == 1
+        static[:, 9] = gen >= 2
     static[:, 3] = t
     static[:, 4] = path
     static[:, 6] = (lengths * (1.0 - t) + rem) / r_in / 40.0
-    static[:, 7] = gen == 0
-    static[:, 8] = gen == 1
-    static[:, 9] = gen >= 2
-    return SiteFrame(static, sid, a, radial, azim)
+    return SiteFrame(static, r, sid, a, radial, azim)
 
 
 def features(frame: SiteFrame, k_seg: Sequence[float], u0: float, phase: float,
@@ -322,7 +348,7 @@ def network_prior(geo: inputs.Geometry, frame: SiteFrame, k_seg, F: float, P0: f
     row = np.empty(int(idx.max()) + 1, np.int64)
     row[idx] = np.arange(n)
     g = row[seg]
-    r = 24.0 * st[:, 1].astype(np.float64)
+    r = frame.r.astype(np.float64)
     t = st[:, 3].astype(np.float64)
     dist = np.maximum(r * (1.0 - st[:, 0]), 0.0)
     pos = t * n_sub
@@ -420,7 +446,7 @@ def run_to_periodic(lat: lbm.Lattice, n_inst: int, period: int, tol: float = 1e-
 
 # ----------------------------------------------------------- training ----
 def collect_batch(wl: workloads.Workload, dtype="f16", phases=8, sites_per_phase=2048,
-                  tol=1e-3, max_cycles=20, seed=0, log=None):
+                  tol=1e-3, max_cycles=20, seed=0, log=None, feature_set="absolute"):
     """Runs a batch of instances cold to periodicity, then samples every
     instance at `phases` phases of one further cycle.  Returns (X, T,
     PeriodicResult).  All instances share the drive period."""
@@ -432,11 +458,11 @@ def collect_batch(wl: workloads.Workload, dtype="f16", phases=8, sites_per_phase
     res = run_to_periodic(lat, len(wl.geoms), period, tol, max_cycles, log=log)
     subs = []
     for k, g in enumerate(wl.geoms):
-        fr = site_frames(g)
+        fr = site_frames(g, feature_set)
         n = fr.static.shape[0]
         idx = np.sort(rng.choice(n, min(sites_per_phase, n), replace=False))
-        subs.append((idx, SiteFrame(fr.static[idx], fr.seg[idx], fr.axis[idx], fr.radial[idx],
-                                    fr.azim[idx])))
+        subs.append((idx, SiteFrame(fr.static[idx], fr.r[idx], fr.seg[idx], fr.axis[idx],
+                                    fr.radial[idx], fr.azim[idx])))
     Xs, Ts = [], []
     step = period // phases
     for ph in range(phases):
@@ -462,15 +488,18 @@ GEN_SLOTS = range(7, 10)
 TRUST = 1.0
 
 
-def new_net(seed=0, width=128, depth=4):
-    """Network with the standard shape; the first-layer weights of the
-    generation one-hot inputs start at zero, so generations absent from
-    the training data contribute nothing at inference."""
+def new_net(seed=0, width=128, depth=4, feature_set="absolute"):
+    """Network with the standard shape for the given feature set; the
+    first-layer weights of the generation one-hot inputs start at zero, so
+    generations absent from the training data contribute nothing at
+    inference."""
     from . import mlp
     p = mlp.init_params(N_FEAT, width, depth, N_OUT, seed=seed)
     W0 = p[:N_FEAT * width].reshape(width, N_FEAT)
     W0[:, list(GEN_SLOTS)] = 0.0
-    return mlp.Net(N_FEAT, width, depth, N_OUT, params=p)
+    net = mlp.Net(N_FEAT, width, depth, N_OUT, params=p)
+    net.feature_set = feature_set
+    return net
 
 
 def feature_range(X: np.ndarray, margin: float = 0.05) -> np.ndarray:
@@ -576,7 +605,7 @@ def compare_starts(net, wl: workloads.Workload, dtype="f32", tol=1e-3, max_cycle
     frames, priors = {}, {}
     if any(m != "cold" for m in modes):
         for k, (g, p) in enumerate(zip(wl.geoms, wl.params)):
-            frames[k] = site_frames(g)
+            frames[k] = site_frames(g, getattr(net, "feature_set", "absolute"))
             priors[k] = instance_prior(g, frames[k], p, 0.0, nu)
     try:
         for mode in modes:
@@ -619,8 +648,10 @@ NET_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "war
 
 
 def save_net_file(path, net):
-    """Parameters and training-feature range of a network (.npz)."""
-    np.savez(path, params=net.state(), feature_range=net.feature_range)
+    """Parameters, training-feature range and feature set of a network
+    (.npz; no object arrays)."""
+    np.savez(path, params=net.state(), feature_range=net.feature_range,
+             feature_set=np.array(getattr(net, "feature_set", "absolute")))
 
 
 def load_net(state):
@@ -630,6 +661,7 @@ def load_net(state):
     if hasattr(state, "keys"):
         net = mlp.Net(N_FEAT, 128, 4, N_OUT, params=np.asarray(state["params"], np.float64))
         net.feature_range = np.asarray(state["feature_range"], np.float64)
+        net.feature_set = str(state["feature_set"]) if "feature_set" in state else "absolute"
         return net
     return mlp.Net(N_FEAT, 128, 4, N_OUT, params=np.asarray(state, np.float64))
 
@@ -676,7 +708,7 @@ def summarize(results):
 def experiment(train_batches=4, train_per_batch=64, train_sites=20e6, test_sweep=16,
                test_sweep_sites=5e6, test_trees=16, tree_first=0, tree_scale=1.0, dtype="f32",
                epochs=30, sites_per_phase=2048, max_cycles=12, seed=0, net_params=None,
-               save_net=None, checkpoint=None, log=print):
+               save_net=None, checkpoint=None, log=print, feature_set="absolute"):
     """Train on cold-started sweep batches (seeds 1000.., run to
     periodicity, sampled at 8 phases) unless `net_params` is given, then
     start held-out sweep instances (seed 3000) and Murray trees (seeds
@@ -691,14 +723,14 @@ def experiment(train_batches=4, train_per_batch=64, train_sites=20e6, test_sweep
                            test_sweep_sites=test_sweep_sites, test_trees=test_trees,
                            tree_first=tree_first, tree_scale=tree_scale, dtype=dtype,
                            epochs=epochs, sites_per_phase=sites_per_phase, tol=1e-3,
-                           period=int(workloads.PERIOD)))
+                           period=int(workloads.PERIOD), feature_set=feature_set))
     if net_params is None:
         Xs, Ts, train_cycles = [], [], []
         t0 = time.perf_counter()
         for b in range(train_batches):
             wl = workloads.sweep(seed=1000 + b, n=train_per_batch, target_sites=train_sites)
             X, T, res = collect_batch(wl, dtype, sites_per_phase=sites_per_phase,
-                                      max_cycles=max_cycles, seed=b)
+                                      max_cycles=max_cycles, seed=b, feature_set=feature_set)
             Xs.append(X)
             Ts.append(T)
             train_cycles += res.cycles
@@ -706,7 +738,7 @@ def experiment(train_batches=4, train_per_batch=64, train_sites=20e6, test_sweep
                 f"median {np.median(res.cycles):.0f}, {res.seconds:.1f}s")
         X, T = np.concatenate(Xs), np.concatenate(Ts)
         t_data = time.perf_counter() - t0
-        net = new_net(seed=seed)
+        net = new_net(seed=seed, feature_set=feature_set)
         t0 = time.perf_counter()
         losses = train(net, X, T, epochs=epochs, log=lambda m: log("[warmstart] " + m)
                        if m.startswith("epoch") and (int(m.split()[1][:-1]) % 5 == 0) else None)
@@ -720,6 +752,7 @@ def experiment(train_batches=4, train_per_batch=64, train_sites=20e6, test_sweep
         log(f"[warmstart] data {t_data:.0f}s, training {out['train']['seconds_train']:.0f}s")
     else:
         net = load_net(net_params)
+        out["config"]["feature_set"] = net.feature_set
     results = {}
     blank = lambda: dict(state_diff=[], sites=[], **{k: [] for m in MODES
                                                       for k in (m, m + "_du", m + "_dp")})
@@ -767,6 +800,8 @@ def main(argv=None):
     ap.add_argument("--out", default=None, help="write the full result (JSON)")
     ap.add_argument("--merge", nargs="+", default=None,
                     help="only combine the per-instance results of earlier --out files")
+    ap.add_argument("--features", choices=FEATURE_SETS, default="absolute",
+                    help="feature set of a network trained here (a loaded one keeps its own)")
     ap.add_argument("--out-of-range", choices=("gate", "clamp"), default="gate",
                     help="sites with features outside the training range: no correction "
                          "(gate) or features clamped into the range (clamp)")
@@ -792,7 +827,8 @@ def main(argv=None):
         r, net = experiment(a.train_batches, a.train_per_batch, a.train_sites, a.test_sweep,
                             a.test_sweep_sites, a.test_trees, a.tree_first, a.tree_scale,
                             a.dtype, a.epochs, net_params=p, save_net=a.save_net,
-                            checkpoint=save, log=lambda m: print(m, flush=True))
+                            checkpoint=save, log=lambda m: print(m, flush=True),
+                            feature_set=a.features)
     if a.out:
         with open(a.out, "w") as f:
             f.write(json.dumps(r) + "\n")

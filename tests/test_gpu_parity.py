@@ -185,7 +185,8 @@ def test_single_site_instances():
 @pytest.mark.parametrize("fused", [1, 0])
 def test_launch_configurations_are_bit_identical(fused):
     """Block size, addressing (compressed, 16- or 32-bit table), graph replay,
-    XCD remapping and non-temporal stores change only the schedule, never
+    the block order over the XCDs (launch order, one range per XCD, runs of
+    4 or 64 blocks) and non-temporal stores change only the schedule, never
     the arithmetic."""
     p = H.tube_problem(10, 40, seed=6)
     ref = None
@@ -194,7 +195,9 @@ def test_launch_configurations_are_bit_identical(fused):
                 dict(block_size=1024, index_bits=16, use_graph=1, xcd_remap=0, nontemporal=0),
                 dict(block_size=512, index_bits=32, use_graph=1, xcd_remap=1, nontemporal=1),
                 dict(block_size=128, index_bits=0, use_graph=1, xcd_remap=1, nontemporal=0),
-                dict(block_size=1024, index_bits=0, use_graph=0, xcd_remap=0, nontemporal=1)]:
+                dict(block_size=1024, index_bits=0, use_graph=0, xcd_remap=0, nontemporal=1),
+                dict(block_size=64, index_bits=0, use_graph=1, xcd_remap=4, nontemporal=1),
+                dict(block_size=256, index_bits=32, use_graph=1, xcd_remap=64, nontemporal=0)]:
         lat = H.make_lattice([p], "f32")
         lat.set_launch(boundary_fused=fused, **cfg)
         lat.step(300)

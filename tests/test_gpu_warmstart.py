@@ -52,6 +52,7 @@ def test_trained_network_beats_the_prior_on_held_out_instances():
     import numpy as np
     from paper_2108_08783_amd import warmstart, workloads
     net = warmstart.load_net(dict(np.load(warmstart.NET_FILE)))
+    assert net.feature_set == "absolute"
     wl = workloads.sweep(seed=3000, n=16, target_sites=5e6)
     cmp = warmstart.compare_starts(net, wl, "f32", max_cycles=12, log=print)
     cyc = {m: cmp[m].cycles for m in warmstart.MODES}

@@ -72,7 +72,7 @@ def test_prior_mean_flow_conserves_the_inlet_flow():
     g, fr = _tube()
     u0 = 0.02
     P = warmstart.network_prior(g, fr, [1e9], 0.85, 1 / 3, u0, 0.0, nu=NU, amp=0.0)
-    r = 24.0 * fr.static[:, 1]
+    r = fr.r
     for lo in (0.2, 0.5, 0.8):
         sel = _section(fr, lo, lo + 0.02)
         # area-weighted mean axial velocity over the disk: the profile is
@@ -128,8 +128,43 @@ def test_feature_layout():
     assert X.shape == (fr.static.shape[0], warmstart.N_FEAT)
     assert np.array_equal(X[:, 5], P.Y[:, 0]) and np.array_equal(X[:, 10], P.Y[:, 1])
     assert np.array_equal(X[:, 11], P.slip)
-    assert np.all(X[:, 7] == 1.0) and np.all(X[:, 8:10] == 0.0)     # one generation-0 tube
+    # one generation-0 tube of radius 8: absolute radius, radius over the
+    # inlet's, the generation one-hot
+    assert np.allclose(X[:, 1], 8.0 / 24.0) and np.allclose(X[:, 2], 1.0)
+    assert np.all(X[:, 7] == 1.0) and np.all(X[:, 8:10] == 0.0)
+    # the scale-free set: radius over the reference, generation 0, slots 7-9 unused
+    Xs = warmstart.features(warmstart.site_frames(g, "scale_free"), [0.01], 0.02, 0.1, P)
+    assert np.all(Xs[:, 1] == 1.0) and np.all(Xs[:, 2] == 0.0) and np.all(Xs[:, 7:10] == 0.0)
+    assert np.array_equal(np.delete(Xs, [1, 2, 7, 8, 9], 1), np.delete(X, [1, 2, 7, 8, 9], 1))
     assert np.allclose(X[:, 14], math.sin(0.2 * math.pi)) and np.allclose(X[:, 15], math.cos(0.2 * math.pi))
+
+
+def test_tree_features_are_free_of_the_scale():
+    """With the scale-free feature set, on a Murray tree the radius feature
+    is r(t) over the parent's end
+    radius and the generation feature is the segment's generation; both,
+    and the other geometric features, take the same values per segment at
+    half and at full scale (the held-out trees are larger than the training
+    vessels, so an absolute radius would put them outside the range)."""
+    stats = []
+    for scale in (0.5, 1.0):
+        g = inputs.murray_tree(2000, scale=scale)
+        fr = warmstart.site_frames(g, "scale_free")
+        segs = {sg.sid: sg for sg in g.segments}
+        parent, _ = warmstart._topology(g.segments)
+        rref = {sg.sid: (g.segments[parent[j]].r1 if parent[j] >= 0 else sg.r0)
+                for j, sg in enumerate(g.segments)}
+        ref = np.array([rref[int(s)] for s in fr.seg])
+        assert np.allclose(fr.static[:, 1], fr.r / ref, rtol=1e-6)
+        gen = np.array([segs[int(s)].gen for s in fr.seg])
+        assert np.array_equal(fr.static[:, 2], gen.astype(np.float32))
+        assert np.all(fr.static[:, 7:10] == 0.0)
+        # per-segment mean of the scale-free geometric features
+        ids = sorted(segs)
+        stats.append(np.array([[fr.static[fr.seg == i][:, j].mean() for j in (1, 2, 3, 4)]
+                               for i in ids]))
+    assert stats[0].shape == stats[1].shape
+    assert np.abs(stats[0] - stats[1]).max() < 0.08
 
 
 def test_feature_range_gate():
