@@ -28,7 +28,7 @@ def test_workload_table_names_the_three_workloads():
         assert "elastic" in text and "tau=0.8" in text
 
 
-@pytest.mark.parametrize("tag", ["tube32", "tree"])
+@pytest.mark.parametrize("tag", ["tree", "sweep64"])
 def test_committed_traffic_records_are_well_formed(tag):
     """Each record holds FETCH_SIZE / WRITE_SIZE per dispatch for FP32 and
     FP16 storage, scaled by the copy reference (fetch x2, write x1), and the

@@ -520,6 +520,8 @@ def test_invalid_arguments_are_rejected_and_leave_the_context_usable():
                                                          period=0.0),
         "block size": lambda: lat.set_launch(block_size=96),
         "index width": lambda: lat.set_launch(index_bits=8),
+        "XCD run length not a power of two": lambda: lat.set_launch(xcd_remap=24),
+        "XCD run length too long": lambda: lat.set_launch(xcd_remap=8192),
         "negative step count": lambda: lat.step(-1),
         "read-out of a missing instance": lambda: lat.read_fields(3),
     }
