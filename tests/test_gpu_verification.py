@@ -3,22 +3,28 @@ Table A1: R = 50 lattice spacings, tau = 0.537, alpha = 3, 5.2M sites):
 after three periods the rigid run follows the rigid Womersley solution,
 and the elastic run follows the elastic-tube shape with M from the Sec. 2.3
 relation at the paper's F = 0.85, better than the rigid shape and, at the
-median phase, within the paper's error level of 10 %."""
+median phase, within the paper's error level of 10 %.  One run per test
+(about 95 s each on one MI355X)."""
 import pytest
 
 pytestmark = pytest.mark.gpu
 
 
-def test_womersley_rigid_and_elastic_shapes_at_the_papers_tau():
+def test_womersley_rigid_at_the_papers_tau():
     from paper_2108_08783_amd import lbm, verification
     rigid = verification.womersley(50, lbm.BOUNCEBACK, log=print)
-    elastic = verification.womersley(50, lbm.ELASTIC, log=print)
-    assert abs(rigid["tau"] - 0.537) < 5e-4 and abs(elastic["tau"] - 0.537) < 5e-4
-    # rigid: measured-gradient Womersley solution and the fitted rigid shape
+    assert abs(rigid["tau"] - 0.537) < 5e-4
+    # measured-gradient Womersley solution and the fitted rigid shape
     assert max(p["err_rel_amplitude"] for p in rigid["phases"]) < 0.03
     assert rigid["shape_fits"]["rigid_model"]["err_max_rel_amplitude"] < 0.03
-    # elastic: the elastic shape fits to the paper's level, and better than
-    # the rigid one
+
+
+def test_womersley_elastic_shape_at_the_papers_tau():
+    from paper_2108_08783_amd import lbm, verification
+    elastic = verification.womersley(50, lbm.ELASTIC, log=print)
+    assert abs(elastic["tau"] - 0.537) < 5e-4
+    # the elastic shape fits to the paper's level, and better than the
+    # rigid one
     fe = elastic["shape_fits"]["elastic_model"]["err_max_rel_amplitude"]
     fr = elastic["shape_fits"]["rigid_model"]["err_max_rel_amplitude"]
     per_phase = sorted(elastic["shape_fits"]["elastic_model"]["phase_err_rel_amplitude"])
