@@ -174,7 +174,8 @@ def summary(r, dtype, with_traffic=False):
                window_launches=r["window"],
                index_bits=r["info"]["index_bits"], block=r["info"]["block_size"],
                xcd_remap=r["info"]["xcd_remap"], nontemporal=r["info"]["nontemporal"],
-               fused=r["info"]["boundary_fused"], boundary_sites=r["info"]["n_boundary"])
+               fused=r["info"]["boundary_fused"], sites_per_lane=r["info"]["sites_per_lane"],
+               boundary_sites=r["info"]["n_boundary"])
     if with_traffic:
         out["traffic"] = traffic_from_profiles(dtype, with_traffic)
     return out
@@ -354,7 +355,7 @@ def main():
                     sites=n, boundary_sites=info["n_boundary"], storage=dtype,
                     index_bits=info["index_bits"], block=info["block_size"],
                     xcd_remap=info["xcd_remap"], nontemporal=info["nontemporal"],
-                    boundary_fused=info["boundary_fused"],
+                    boundary_fused=info["boundary_fused"], sites_per_lane=info["sites_per_lane"],
                     timed_steps_graph_replayed=args.steps >= 128, parallelism="single GPU",
                     autotune_trial_steps=MAIN_TUNE_STEPS),
         roofline=roofline,

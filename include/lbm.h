@@ -333,8 +333,11 @@ int lbm_instance_sites(const lbm_ctx* ctx, int inst, int64_t* n);
  * the same blocks as all other sites, which apply the link rules in place;
  * 0: they are skipped there and updated by a compacted list of boundary
  * sites in blocks appended to the same launch.  Both modes compute the same
- * link rule.  sites_per_lane: 1 (the only value accepted; two
- * sites per lane measured slower on gfx950).  A value of -1 keeps the
+ * link rule.  sites_per_lane: 1, or 2 for FP32 storage with index_bits 0,
+ * boundary_fused 1 and population buffers below 2 GiB (else LBM_EINVAL):
+ * each wavefront then updates 128 consecutive sites, lane l the sites x and
+ * x + 64, with the two loads of every direction issued back to back (the
+ * 128-byte line they share is fetched once).  A value of -1 keeps the
  * current setting.  No setting changes the arithmetic. */
 int lbm_set_launch(lbm_ctx* ctx, int block_size, int index_bits, int use_graph, int xcd_remap,
                    int nontemporal, int boundary_fused, int sites_per_lane);

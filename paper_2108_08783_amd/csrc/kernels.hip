@@ -675,6 +675,106 @@ void k_step(StepArgs a) {
     if (b == 0 && threadIdx.x == 0) a.clock[a.clock_in ^ 1] = a.clock[a.clock_in] + 1;
 }
 
+// --------------------------------------------------------- site pairs ---
+// Two sites per lane (32-bit storage): each wavefront updates a tile of 128
+// consecutive sites, lane l the sites x and x + 64.  Each direction's 64
+// consecutive entries start at an arbitrary offset, so one wavefront's load
+// touches one 128-byte line more than its 256 bytes need; the two loads of
+// a direction are issued back to back here, and the line they share is
+// fetched once.  The arithmetic is k_step's.
+
+// Pulled slots of site x as in pull_slots (compressed addressing, the
+// 64 sites of x's record in one half-tile).  A lane past the last site
+// (act false) gets the own-slot offsets of a site inside the buffer and no
+// boundary record; its results are not stored.
+template <int DT>
+__device__ __forceinline__ void pair_slots(const StepArgs& a, int x, bool act, uint32_t (&o)[18],
+                                           bool& ghost, int& rec) {
+    constexpr uint32_t S = sizeof(typename Codec<DT>::raw);
+    const uint32_t np = (uint32_t)a.np;
+    const int xs = act ? x : min(x, (int)np - 1);
+    const uint32_t own = ((uint32_t)xs + np + 1u) * S;
+    const uint32_t xr = ((uint32_t)xs + 1u) * S;
+    const int w = __builtin_amdgcn_readfirstlane(x >> 6);
+    const int l = x & 63;
+    const WfRec r = a.wf[w];
+    const uint64_t bit = 1ull << l, below = bit - 1ull;
+    int st = r.cur + __popcll(r.smask & (bit | below));
+    st = st < 0 ? 0 : st;
+    const int4* SP = (const int4*)((const char*)a.stretch + (uint64_t)((uint32_t)st * 32u));
+    const int4 s0 = SP[0], s1 = SP[1];
+    uint32_t nf = 0;
+    rec = -1;
+    if ((r.imask & bit) && act) {
+        rec = r.firr + __popcll(r.imask & below);
+        nf = *(const uint32_t*)((const char*)a.nfm + (uint64_t)((uint32_t)rec * 4u));
+    }
+    if (!act) nf = 0x3FFFFu;   // every link reads the own opposite slot
+    const int32_t D[8] = {s0.x, s0.y, s0.z, s0.w, s1.x, s1.y, s1.z, s1.w};
+    uint32_t row[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) row[k] = own + (uint32_t)D[k] * S;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const int rs = row_slot(i);
+        const uint32_t n = rs < 0 ? own : row[rs];
+        const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe((int)nf, i - 1, 1);
+        o[i - 1] = (m & redirect_off<DT>(i, xr, np)) | (~m & n);
+    }
+    ghost = (int32_t)nf < 0;
+    if ((r.emask & bit) && act) {
+        const int e = r.fexc + __popcll(r.emask & below);
+        const uint64_t eo = (uint32_t)e * 4u;
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            const int32_t v = *(const int32_t*)((const char*)(a.exc + (int64_t)(i - 1) * a.n_exc_pad) + eo);
+            o[i - 1] = v <= Sentinel<int32_t>::GHOST
+                           ? redirect_off<DT>(i, xr, np)
+                           : ((uint32_t)(x + v + CX[i]) + np + 1u) * S;
+        }
+    }
+}
+
+template <int DT, bool NTL>
+__global__ __launch_bounds__(1024) void k_step_pair(StepArgs a) {
+    using raw = typename Codec<DT>::raw;
+    using acc = typename Codec<DT>::acc;
+    constexpr uint32_t S = sizeof(raw);
+    static_assert(S == 4, "site pairs are built for 32-bit storage");
+    const int b = blockIdx.x;
+    if (b == 0 && threadIdx.x == 0) a.clock[a.clock_in ^ 1] = a.clock[a.clock_in] + 1;
+    const int lb = remap_block(b, a.n_int_blocks, a.xcd_remap);
+    const int wv = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
+    const int t0 = lb * 2 * (int)blockDim.x + wv * 128;   // first site of the wavefront's tile
+    const int x0 = t0 + lane, x1 = x0 + 64;
+    // a half-tile without any site is left out (uniform across the wavefront)
+    if (t0 >= a.n) return;
+    const bool any1 = t0 + 64 < a.n;
+    const bool v0 = x0 < a.n, v1 = x1 < a.n;
+    uint32_t o0[18], o1[18];
+    bool g0, g1 = false;
+    int r0, r1 = -1;
+    pair_slots<DT>(a, x0, v0, o0, g0, r0);
+    if (any1) pair_slots<DT>(a, x1, v1, o1, g1, r1);
+    BRec<acc> br0, br1;
+    if (g0) br0 = load_brec<acc>(a, r0);
+    if (g1) br1 = load_brec<acc>(a, r1);
+    acc h0[Q], h1[Q];
+    const char* base = (const char*)a.A;
+    const int64_t np = a.np;
+    const uint32_t xs0 = v0 ? (uint32_t)x0 : 0u, xs1 = v1 ? (uint32_t)x1 : 0u;
+    h0[0] = Codec<DT>::sdec(ld<raw, NTL>((const raw*)(base + (uint64_t)(xs0 * S))));
+    if (any1) h1[0] = Codec<DT>::sdec(ld<raw, NTL>((const raw*)(base + (uint64_t)(xs1 * S))));
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        const char* P = base + ((int64_t)i * np - CX[i] - np - 1) * (int64_t)S;
+        h0[i] = Codec<DT>::sdec(ld<raw, NTL>((const raw*)(P + (uint64_t)o0[i - 1])));
+        if (any1) h1[i] = Codec<DT>::sdec(ld<raw, NTL>((const raw*)(P + (uint64_t)o1[i - 1])));
+    }
+    if (v0) collide_store<DT, true>(a, x0, g0, r0, h0, br0);
+    if (v1) collide_store<DT, true>(a, x1, g1, r1, h1, br1);
+}
+
 // ------------------------------------------------------------ read-out ---
 template <int DT, typename I>
 __global__ __launch_bounds__(256) void k_fields(FieldArgs a) {
@@ -914,6 +1014,18 @@ hipError_t dispatch(int dtype, int ibits, Args&&... args) {
 
 template <int DT, int ADDR>
 hipError_t step_launch(const StepArgs& a, int block, hipStream_t s) {
+    if (a.spt == 2) {
+        // the runtime checked: 32-bit storage, compressed addressing, fused
+        // boundary mode, buffers below 2 GiB, n_int_blocks = ceil(n / 2 block)
+        if constexpr (ADDR == ADDR_COMP && DT == LBM_F32) {
+            if ((a.nontemporal & 2) != 0)
+                hipLaunchKernelGGL((k_step_pair<DT, true>), dim3(a.n_int_blocks), dim3(block), 0, s, a);
+            else
+                hipLaunchKernelGGL((k_step_pair<DT, false>), dim3(a.n_int_blocks), dim3(block), 0, s, a);
+            return hipGetLastError();
+        }
+        return hipErrorInvalidValue;
+    }
     const int nb_blocks = a.fused ? 0 : cdiv(a.nb, block);
     // 32-bit byte offsets when a population buffer is below 2^31 bytes
     const bool small = (int64_t)Q * a.np * (int64_t)sizeof(typename Codec<DT>::raw) < (1ll << 31);

@@ -53,7 +53,7 @@ struct StepArgs {
     int32_t nontemporal;
     int32_t clock_in;       // clock slot read this step; the other is written
     int32_t fused;          // 1: boundary links applied inside the update blocks
-    int32_t spt;            // sites per lane in the update blocks (1 or 2)
+    int32_t spt;            // sites per lane: 1, or 2 (tiles of 128 sites, 32-bit storage)
     double omega;           // 1 / tau
     const int32_t* bj;      // record ids of sites with boundary-pass links (compacted mode)
     const int32_t* rsite;   // record id -> site

@@ -1317,8 +1317,19 @@ int lbm_set_launch(lbm_ctx* c, int block_size, int index_bits, int use_graph, in
         return fail(c, LBM_EINVAL, "block size %d not supported", block_size);
     if (index_bits != -1 && index_bits != 0 && index_bits != 16 && index_bits != 32)
         return fail(c, LBM_EINVAL, "index_bits must be 0 (compressed), 16 or 32");
-    if (sites_per_lane != -1 && sites_per_lane != 1)
-        return fail(c, LBM_EINVAL, "sites_per_lane must be 1");
+    if (sites_per_lane != -1 && sites_per_lane != 1 && sites_per_lane != 2)
+        return fail(c, LBM_EINVAL, "sites_per_lane must be 1 or 2");
+    {
+        // two sites per lane: FP32 storage, compressed addressing, the fused
+        // boundary mode and population buffers below 2 GiB
+        const int spt = sites_per_lane != -1 ? sites_per_lane : c->spt;
+        const int ib = index_bits != -1 ? index_bits : c->ibits;
+        const int fu = boundary_fused != -1 ? (boundary_fused ? 1 : 0) : c->fused;
+        if (spt == 2 && (c->dtype != LBM_F32 || ib != 0 || !fu ||
+                         (int64_t)Q * c->np * (int64_t)c->esize >= (1ll << 31)))
+            return fail(c, LBM_EINVAL, "sites_per_lane 2 needs FP32 storage, index_bits 0, "
+                                       "boundary_fused 1 and population buffers below 2 GiB");
+    }
     if (xcd_remap != -1 && xcd_remap != 0 && xcd_remap != 1 &&
         (xcd_remap < 2 || xcd_remap > 4096 || (xcd_remap & (xcd_remap - 1))))
         return fail(c, LBM_EINVAL, "xcd_remap must be 0, 1 or a power of two up to 4096");
@@ -1386,6 +1397,11 @@ int lbm_autotune(lbm_ctx* c, int steps_per_trial, double* best_rate) {
                     for (int ntv = 0; ntv < 2; ++ntv) trials.push_back(TuneVal{bs, ib, xr, ntv, fu, 1});
                 }
     }
+    // two sites per lane where they apply (FP32, compressed, fused)
+    if (c->dtype == LBM_F32 && (int64_t)Q * c->np * (int64_t)c->esize < (1ll << 31))
+        for (int bs : {128, 256, 512})
+            for (int xr : {0, 1, 4, 16})
+                for (int ntv = 0; ntv < 2; ++ntv) trials.push_back(TuneVal{bs, 0, xr, ntv, 1, 2});
     for (const TuneVal& v : trials) {
         rc = lbm_set_launch(c, v.block, v.ibits, -1, v.xcd, v.nt, v.fused, v.spt);
         if (rc) break;

@@ -207,6 +207,43 @@ def test_launch_configurations_are_bit_identical(fused):
             ref = f
         else:
             assert np.array_equal(f, ref), cfg
+    if fused:
+        # two sites per lane (FP32, compressed addressing, fused mode)
+        for cfg in [dict(block_size=256, index_bits=0, use_graph=1, xcd_remap=4, nontemporal=0,
+                         sites_per_lane=2),
+                    dict(block_size=128, index_bits=0, use_graph=0, xcd_remap=0, nontemporal=1,
+                         sites_per_lane=2),
+                    dict(block_size=512, index_bits=0, use_graph=1, xcd_remap=1, nontemporal=3,
+                         sites_per_lane=2)]:
+            lat = H.make_lattice([p], "f32")
+            lat.set_launch(boundary_fused=fused, **cfg)
+            assert lat.info()["sites_per_lane"] == 2
+            lat.step(300)
+            f = lat.read_populations(0)
+            lat.close()
+            assert np.array_equal(f, ref), cfg
+
+
+@pytest.mark.parametrize("seed", [1, 2, 5])
+def test_two_sites_per_lane_on_random_boxes(seed):
+    """Two sites per lane on random boxes (a few hundred sites: partial
+    tiles and empty half-tiles, exceptional rows, every link type): the
+    same populations as one site per lane, bit for bit, and the oracle's
+    fields to the FP32 bound after 60 steps."""
+    p = H.random_box_problem(seed)
+    out = []
+    for spt in (1, 2):
+        lat = H.make_lattice([p], "f32")
+        lat.set_launch(index_bits=0, boundary_fused=1, block_size=128, sites_per_lane=spt)
+        lat.step(60)
+        out.append((lat.read_populations(0), lat.read_fields(0)))
+        lat.close()
+    assert np.array_equal(out[0][0], out[1][0])
+    o = H.make_oracle(p)
+    o.step(60)
+    e = H.errors(out[1][1], o.read(), P0=p.P0)
+    record(f"random_box_{seed}_two_sites_per_lane", e, dtype="f32", steps=60)
+    assert e["u"] <= TOL["f32"] and e["p"] <= TOL["f32"] and e["wss"] <= TOL["f32"]
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f16"])
@@ -521,6 +558,9 @@ def test_invalid_arguments_are_rejected_and_leave_the_context_usable():
         "block size": lambda: lat.set_launch(block_size=96),
         "index width": lambda: lat.set_launch(index_bits=8),
         "XCD run length not a power of two": lambda: lat.set_launch(xcd_remap=24),
+        "three sites per lane": lambda: lat.set_launch(sites_per_lane=3),
+        "two sites per lane with an offset table": lambda: lat.set_launch(index_bits=32,
+                                                                          sites_per_lane=2),
         "XCD run length too long": lambda: lat.set_launch(xcd_remap=8192),
         "negative step count": lambda: lat.step(-1),
         "read-out of a missing instance": lambda: lat.read_fields(3),
