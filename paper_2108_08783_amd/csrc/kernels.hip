@@ -747,15 +747,16 @@ __global__ __launch_bounds__(1024) void k_step_pair(StepArgs a) {
     const int wv = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
     const int t0 = lb * 2 * (int)blockDim.x + wv * 128;   // first site of the wavefront's tile
     const int x0 = t0 + lane, x1 = x0 + 64;
-    // a half-tile without any site is left out (uniform across the wavefront)
+    // a tile without any site is left out (uniform across the wavefront);
+    // tiles start at multiples of 128 and the planes hold a multiple of 256
+    // entries, so both halves of a started tile lie inside the planes
     if (t0 >= a.n) return;
-    const bool any1 = t0 + 64 < a.n;
     const bool v0 = x0 < a.n, v1 = x1 < a.n;
     uint32_t o0[18], o1[18];
-    bool g0, g1 = false;
-    int r0, r1 = -1;
+    bool g0, g1;
+    int r0, r1;
     pair_slots<DT>(a, x0, v0, o0, g0, r0);
-    if (any1) pair_slots<DT>(a, x1, v1, o1, g1, r1);
+    pair_slots<DT>(a, x1, v1, o1, g1, r1);
     BRec<acc> br0, br1;
     if (g0) br0 = load_brec<acc>(a, r0);
     if (g1) br1 = load_brec<acc>(a, r1);
@@ -764,12 +765,12 @@ __global__ __launch_bounds__(1024) void k_step_pair(StepArgs a) {
     const int64_t np = a.np;
     const uint32_t xs0 = v0 ? (uint32_t)x0 : 0u, xs1 = v1 ? (uint32_t)x1 : 0u;
     h0[0] = Codec<DT>::sdec(ld<raw, NTL>((const raw*)(base + (uint64_t)(xs0 * S))));
-    if (any1) h1[0] = Codec<DT>::sdec(ld<raw, NTL>((const raw*)(base + (uint64_t)(xs1 * S))));
+    h1[0] = Codec<DT>::sdec(ld<raw, NTL>((const raw*)(base + (uint64_t)(xs1 * S))));
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
         const char* P = base + ((int64_t)i * np - CX[i] - np - 1) * (int64_t)S;
         h0[i] = Codec<DT>::sdec(ld<raw, NTL>((const raw*)(P + (uint64_t)o0[i - 1])));
-        if (any1) h1[i] = Codec<DT>::sdec(ld<raw, NTL>((const raw*)(P + (uint64_t)o1[i - 1])));
+        h1[i] = Codec<DT>::sdec(ld<raw, NTL>((const raw*)(P + (uint64_t)o1[i - 1])));
     }
     if (v0) collide_store<DT, true>(a, x0, g0, r0, h0, br0);
     if (v1) collide_store<DT, true>(a, x1, g1, r1, h1, br1);
