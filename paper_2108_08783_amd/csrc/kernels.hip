@@ -684,17 +684,24 @@ void k_step(StepArgs a) {
 // fetched once.  The arithmetic is k_step's.
 
 // Pulled slots of site x as in pull_slots (compressed addressing, the
-// 64 sites of x's record in one half-tile).  A lane past the last site
-// (act false) gets the own-slot offsets of a site inside the buffer and no
-// boundary record; its results are not stored.
-template <int DT>
+// 64 sites of x's record in one half-tile), as byte offsets (SMALL: every
+// buffer below 2 GiB) or as element offsets (scaled to bytes in 64 bits at
+// the load).  A lane past the last site (act false) gets the own-slot
+// offsets of a site inside the buffer and no boundary record; its results
+// are not stored.
+template <int DT, bool SMALL>
 __device__ __forceinline__ void pair_slots(const StepArgs& a, int x, bool act, uint32_t (&o)[18],
                                            bool& ghost, int& rec) {
-    constexpr uint32_t S = sizeof(typename Codec<DT>::raw);
+    constexpr uint32_t S = SMALL ? sizeof(typename Codec<DT>::raw) : 1u;
     const uint32_t np = (uint32_t)a.np;
     const int xs = act ? x : min(x, (int)np - 1);
     const uint32_t own = ((uint32_t)xs + np + 1u) * S;
     const uint32_t xr = ((uint32_t)xs + 1u) * S;
+    // the own opposite slot, in the same unit as every other offset here
+    // (redirect_off counts bytes; with element offsets it would not match)
+    const auto red = [&](int i) {
+        return xr + ((dopp(i) > i ? 2u * np : 0u) + (uint32_t)CX[i]) * S;
+    };
     const int w = __builtin_amdgcn_readfirstlane(x >> 6);
     const int l = x & 63;
     const WfRec r = a.wf[w];
@@ -719,7 +726,7 @@ __device__ __forceinline__ void pair_slots(const StepArgs& a, int x, bool act, u
         const int rs = row_slot(i);
         const uint32_t n = rs < 0 ? own : row[rs];
         const uint32_t m = (uint32_t)__builtin_amdgcn_sbfe((int)nf, i - 1, 1);
-        o[i - 1] = (m & redirect_off<DT>(i, xr, np)) | (~m & n);
+        o[i - 1] = (m & red(i)) | (~m & n);
     }
     ghost = (int32_t)nf < 0;
     if ((r.emask & bit) && act) {
@@ -729,13 +736,13 @@ __device__ __forceinline__ void pair_slots(const StepArgs& a, int x, bool act, u
         for (int i = 1; i < Q; ++i) {
             const int32_t v = *(const int32_t*)((const char*)(a.exc + (int64_t)(i - 1) * a.n_exc_pad) + eo);
             o[i - 1] = v <= Sentinel<int32_t>::GHOST
-                           ? redirect_off<DT>(i, xr, np)
+                           ? red(i)
                            : ((uint32_t)(x + v + CX[i]) + np + 1u) * S;
         }
     }
 }
 
-template <int DT, bool NTL>
+template <int DT, bool SMALL, bool NTL>
 __global__ __launch_bounds__(1024) void k_step_pair(StepArgs a) {
     using raw = typename Codec<DT>::raw;
     using acc = typename Codec<DT>::acc;
@@ -755,8 +762,8 @@ __global__ __launch_bounds__(1024) void k_step_pair(StepArgs a) {
     uint32_t o0[18], o1[18];
     bool g0, g1;
     int r0, r1;
-    pair_slots<DT>(a, x0, v0, o0, g0, r0);
-    pair_slots<DT>(a, x1, v1, o1, g1, r1);
+    pair_slots<DT, SMALL>(a, x0, v0, o0, g0, r0);
+    pair_slots<DT, SMALL>(a, x1, v1, o1, g1, r1);
     BRec<acc> br0, br1;
     if (g0) br0 = load_brec<acc>(a, r0);
     if (g1) br1 = load_brec<acc>(a, r1);
@@ -764,16 +771,20 @@ __global__ __launch_bounds__(1024) void k_step_pair(StepArgs a) {
     const char* base = (const char*)a.A;
     const int64_t np = a.np;
     const uint32_t xs0 = v0 ? (uint32_t)x0 : 0u, xs1 = v1 ? (uint32_t)x1 : 0u;
-    h0[0] = Codec<DT>::sdec(ld<raw, NTL>((const raw*)(base + (uint64_t)(xs0 * S))));
-    h1[0] = Codec<DT>::sdec(ld<raw, NTL>((const raw*)(base + (uint64_t)(xs1 * S))));
+    // byte offset of an offset from pair_slots
+    constexpr uint64_t U = SMALL ? 1u : S;
+    const uint64_t e0 = SMALL ? (uint64_t)(xs0 * S) : (uint64_t)xs0 * S;
+    const uint64_t e1 = SMALL ? (uint64_t)(xs1 * S) : (uint64_t)xs1 * S;
+    h0[0] = Codec<DT>::sdec(ld<raw, NTL>((const raw*)(base + e0)));
+    h1[0] = Codec<DT>::sdec(ld<raw, NTL>((const raw*)(base + e1)));
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
         const char* P = base + ((int64_t)i * np - CX[i] - np - 1) * (int64_t)S;
-        h0[i] = Codec<DT>::sdec(ld<raw, NTL>((const raw*)(P + (uint64_t)o0[i - 1])));
-        h1[i] = Codec<DT>::sdec(ld<raw, NTL>((const raw*)(P + (uint64_t)o1[i - 1])));
+        h0[i] = Codec<DT>::sdec(ld<raw, NTL>((const raw*)(P + (uint64_t)o0[i - 1] * U)));
+        h1[i] = Codec<DT>::sdec(ld<raw, NTL>((const raw*)(P + (uint64_t)o1[i - 1] * U)));
     }
-    if (v0) collide_store<DT, true>(a, x0, g0, r0, h0, br0);
-    if (v1) collide_store<DT, true>(a, x1, g1, r1, h1, br1);
+    if (v0) collide_store<DT, SMALL>(a, x0, g0, r0, h0, br0);
+    if (v1) collide_store<DT, SMALL>(a, x1, g1, r1, h1, br1);
 }
 
 // ------------------------------------------------------------ read-out ---
@@ -1017,12 +1028,19 @@ template <int DT, int ADDR>
 hipError_t step_launch(const StepArgs& a, int block, hipStream_t s) {
     if (a.spt == 2) {
         // the runtime checked: 32-bit storage, compressed addressing, fused
-        // boundary mode, buffers below 2 GiB, n_int_blocks = ceil(n / 2 block)
+        // boundary mode, n_int_blocks = ceil(n / 2 block)
         if constexpr (ADDR == ADDR_COMP && DT == LBM_F32) {
-            if ((a.nontemporal & 2) != 0)
-                hipLaunchKernelGGL((k_step_pair<DT, true>), dim3(a.n_int_blocks), dim3(block), 0, s, a);
+            const bool small = (int64_t)Q * a.np * 4 < (1ll << 31);
+            const bool ntl = (a.nontemporal & 2) != 0;
+            const dim3 grid(a.n_int_blocks);
+            if (small && ntl)
+                hipLaunchKernelGGL((k_step_pair<DT, true, true>), grid, dim3(block), 0, s, a);
+            else if (small)
+                hipLaunchKernelGGL((k_step_pair<DT, true, false>), grid, dim3(block), 0, s, a);
+            else if (ntl)
+                hipLaunchKernelGGL((k_step_pair<DT, false, true>), grid, dim3(block), 0, s, a);
             else
-                hipLaunchKernelGGL((k_step_pair<DT, false>), dim3(a.n_int_blocks), dim3(block), 0, s, a);
+                hipLaunchKernelGGL((k_step_pair<DT, false, false>), grid, dim3(block), 0, s, a);
             return hipGetLastError();
         }
         return hipErrorInvalidValue;

@@ -493,7 +493,8 @@ _POP_BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
 
 @pytest.mark.parametrize("dtype,launch", [
     ("f64", None), ("f32", None), ("f16", None), ("bf16", None),
-    ("f32", dict(index_bits=32, boundary_fused=0, nontemporal=0))])
+    ("f32", dict(index_bits=32, boundary_fused=0, nontemporal=0)),
+    ("f32", dict(index_bits=0, boundary_fused=1, block_size=128, sites_per_lane=2))])
 def test_population_buffers_beyond_2GiB(dtype, launch):
     """Three random boxes (every link type; elastic and bounce-back walls)
     packed after a 16-63M-site cylinder, so that their upper population

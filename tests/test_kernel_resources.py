@@ -54,11 +54,12 @@ def test_no_update_kernel_spills_more_than_a_few_registers(resources):
         assert resources[n]["scratch"] <= 16, (n, resources[n])
 
 
+@pytest.mark.parametrize("small", [0, 1])
 @pytest.mark.parametrize("ntl", [0, 1])
-def test_two_sites_per_lane_kernel_has_no_scratch(resources, ntl):
-    # k_step_pair<FP32, non-temporal loads>: two sites' 19 populations and
-    # offsets in registers (5 waves per SIMD), never spilled
-    pat = re.compile(rf"k_step_pairILi1ELb{ntl}E")
+def test_two_sites_per_lane_kernel_has_no_scratch(resources, small, ntl):
+    # k_step_pair<FP32, 32-bit offsets, non-temporal loads>: two sites' 19
+    # populations and offsets in registers (5 waves per SIMD), never spilled
+    pat = re.compile(rf"k_step_pairILi1ELb{small}ELb{ntl}E")
     names = [n for n in resources if pat.search(n)]
     assert len(names) == 1, names
     r = resources[names[0]]
