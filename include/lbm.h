@@ -333,8 +333,8 @@ int lbm_instance_sites(const lbm_ctx* ctx, int inst, int64_t* n);
  * the same blocks as all other sites, which apply the link rules in place;
  * 0: they are skipped there and updated by a compacted list of boundary
  * sites in blocks appended to the same launch.  Both modes compute the same
- * link rule.  sites_per_lane: 1, or 2 for FP32 storage with index_bits 0
- * and boundary_fused 1 (else LBM_EINVAL):
+ * link rule.  sites_per_lane: 1, or 2 for FP32 storage with index_bits 0,
+ * boundary_fused 1 and fewer than 1.4e9 padded sites (else LBM_EINVAL):
  * each wavefront then updates 128 consecutive sites, lane l the sites x and
  * x + 64, with the two loads of every direction issued back to back (the
  * 128-byte line they share is fetched once).  A value of -1 keeps the

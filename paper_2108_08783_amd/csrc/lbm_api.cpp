@@ -1309,6 +1309,10 @@ int lbm_instance_sites(const lbm_ctx* c, int inst, int64_t* n) {
     return LBM_OK;
 }
 
+// The two-sites-per-lane update forms 32-bit slot offsets (bytes below
+// 2 GiB, elements above) of up to about 3 np + 2 elements.
+static bool pair_offsets_fit(int64_t np) { return 3 * np + 4096 < (int64_t)1 << 32; }
+
 int lbm_set_launch(lbm_ctx* c, int block_size, int index_bits, int use_graph, int xcd_remap,
                    int nontemporal, int boundary_fused, int sites_per_lane) {
     if (!c) return fail(nullptr, LBM_EINVAL, "ctx is NULL");
@@ -1320,14 +1324,14 @@ int lbm_set_launch(lbm_ctx* c, int block_size, int index_bits, int use_graph, in
     if (sites_per_lane != -1 && sites_per_lane != 1 && sites_per_lane != 2)
         return fail(c, LBM_EINVAL, "sites_per_lane must be 1 or 2");
     {
-        // two sites per lane: FP32 storage, compressed addressing and the
-        // fused boundary mode
+        // two sites per lane: FP32 storage, compressed addressing, the fused
+        // boundary mode, and 32-bit element offsets (they reach about 3 np)
         const int spt = sites_per_lane != -1 ? sites_per_lane : c->spt;
         const int ib = index_bits != -1 ? index_bits : c->ibits;
         const int fu = boundary_fused != -1 ? (boundary_fused ? 1 : 0) : c->fused;
-        if (spt == 2 && (c->dtype != LBM_F32 || ib != 0 || !fu))
-            return fail(c, LBM_EINVAL, "sites_per_lane 2 needs FP32 storage, index_bits 0 and "
-                                       "boundary_fused 1");
+        if (spt == 2 && (c->dtype != LBM_F32 || ib != 0 || !fu || !pair_offsets_fit(c->np)))
+            return fail(c, LBM_EINVAL, "sites_per_lane 2 needs FP32 storage, index_bits 0, "
+                                       "boundary_fused 1 and fewer than 1.4e9 padded sites");
     }
     if (xcd_remap != -1 && xcd_remap != 0 && xcd_remap != 1 &&
         (xcd_remap < 2 || xcd_remap > 4096 || (xcd_remap & (xcd_remap - 1))))
@@ -1397,7 +1401,7 @@ int lbm_autotune(lbm_ctx* c, int steps_per_trial, double* best_rate) {
                 }
     }
     // two sites per lane where they apply (FP32, compressed, fused)
-    if (c->dtype == LBM_F32)
+    if (c->dtype == LBM_F32 && pair_offsets_fit(c->np))
         for (int bs : {128, 256, 512})
             for (int xr : {0, 1, 4, 16})
                 for (int ntv = 0; ntv < 2; ++ntv) trials.push_back(TuneVal{bs, 0, xr, ntv, 1, 2});
