@@ -9,7 +9,6 @@ gross defects.
 """
 import json
 import os
-import sys
 
 import numpy as np
 import pytest
