@@ -167,6 +167,11 @@ def gpu_run(wl, dtype, steps, warmup, bounceback=False, tune=True, launch=None, 
                 launch_us=roof_ms * 1e3 / (win or steps), window=win or steps)
 
 
+def update_kernel(info):
+    """Name of the update kernel a launch configuration runs."""
+    return "k_step_pair" if info["sites_per_lane"] == 2 else "k_step"
+
+
 def summary(r, dtype, with_traffic=False):
     ach = 2 * 19 * BYTES_PER_POP[dtype] * r["n"] / (r["launch_us"] * 1e-6) / 1e9
     out = dict(sites=r["n"], mlups=round(r["mlups"], 1), us_per_step=round(r["launch_us"], 2),
@@ -273,7 +278,8 @@ def main():
     tr = traffic_from_profiles(dtype, args.workload)
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=PEAK_GBS, unit="GB/s",
                     frac=round(achieved / PEAK_GBS, 4), traffic=tr,
-                    kernel="k_step", window_launches=main_run["window"], graph_replayed=True,
+                    kernel=update_kernel(main_run["info"]), window_launches=main_run["window"],
+                    graph_replayed=True,
                     us_per_launch=round(main_run["launch_us"], 3),
                     algorithmic_bytes_per_launch=alg_bytes)
 
