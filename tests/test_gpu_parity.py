@@ -7,6 +7,7 @@ storage; FP64 storage agrees to rounding (<= 1e-11).  FP16/BF16 deviation
 storage errors are stated (logged) and held to loose bounds that only catch
 gross defects.
 """
+import dataclasses
 import json
 import os
 
@@ -243,6 +244,43 @@ def test_two_sites_per_lane_on_random_boxes(seed):
     e = H.errors(out[1][1], o.read(), P0=p.P0)
     record(f"random_box_{seed}_two_sites_per_lane", e, dtype="f32", steps=60)
     assert e["u"] <= TOL["f32"] and e["p"] <= TOL["f32"] and e["wss"] <= TOL["f32"]
+
+
+# degenerate settings of the elastic rule (Sec. 2.3 and 2.4) on a random box
+# with three stiffness segments
+WALL_LIMITS = {
+    "no_slip_F0": dict(F=0.0),
+    "stiff_k_huge": dict(k=[1e12, 1e12, 1e12]),
+    "soft_k_tiny": dict(k=[1e-8, 1e-8, 1e-8]),
+    "P0_above_every_pressure": dict(P0=0.5),
+}
+
+
+@pytest.mark.parametrize("case", sorted(WALL_LIMITS))
+@pytest.mark.parametrize("dtype,spl", [("f64", 1), ("f32", 1), ("f32", 2)])
+def test_elastic_wall_limits(case, dtype, spl):
+    """The elastic rule at its limits: F = 0 (no slip at the wall node), a
+    stiffness so large that the wall does not move (slip factor F), one so
+    small that the slip factor tends to 1, and an undeformed-wall pressure
+    above every site's pressure (the extension clamped at 0).  GPU against
+    the oracle after 60 steps, one and two sites per lane; the wall
+    position is exactly 1 where the extension vanishes, and grows where
+    the wall is soft."""
+    p = dataclasses.replace(H.random_box_problem(3), **WALL_LIMITS[case])
+    launch = dict(index_bits=0, boundary_fused=1, block_size=128, sites_per_lane=spl)
+    g, r = run_pair(p, dtype, 60, launch=launch)
+    e = H.errors(g, r, P0=p.P0)
+    record(f"wall_limit_{case}", e, dtype=dtype, steps=60, sites_per_lane=spl)
+    tol = TOL[dtype]
+    assert e["u"] <= tol and e["p"] <= tol and e["wss"] <= tol
+    assert e["dr"] <= max(tol, 1e-6)   # the wall position is read out in FP32
+    dr = np.asarray(g[3])
+    wall = dr != 0
+    assert wall.any()
+    if case in ("stiff_k_huge", "P0_above_every_pressure"):
+        assert np.all(dr[wall] == 1.0)
+    if case == "soft_k_tiny":
+        assert dr[wall].max() > 10.0
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f16"])
