@@ -283,6 +283,23 @@ def test_elastic_wall_limits(case, dtype, spl):
         assert dr[wall].max() > 10.0
 
 
+@pytest.mark.parametrize("tau", [0.51, 1.0, 2.0])
+@pytest.mark.parametrize("dtype,spl", [("f64", 1), ("f32", 1), ("f32", 2)])
+def test_relaxation_time_limits(tau, dtype, spl):
+    """The update and read-out away from the usual tau: close to the
+    stability limit 1/2, at tau = 1 (the collision replaces f by feq, so
+    the non-equilibrium part of the read-out comes from the pulled f(t)
+    alone) and at tau = 2; random box with every link type, GPU against
+    the oracle after 60 steps."""
+    p = dataclasses.replace(H.random_box_problem(3), tau=tau)
+    launch = dict(index_bits=0, boundary_fused=1, block_size=128, sites_per_lane=spl)
+    g, r = run_pair(p, dtype, 60, launch=launch)
+    e = H.errors(g, r, P0=p.P0)
+    record(f"random_box_tau_{tau}", e, dtype=dtype, steps=60, sites_per_lane=spl)
+    tol = TOL[dtype]
+    assert e["u"] <= tol and e["p"] <= tol and e["wss"] <= tol
+
+
 @pytest.mark.parametrize("dtype", ["f32", "f16"])
 def test_checkpoint_restart_is_bit_identical(dtype):
     p = H.tube_problem(6, 24, seed=7, pulsatile=False)
