@@ -8,7 +8,7 @@ the fallback and the reference: both starts must converge to the same periodic
 state, and the figure of merit is the number of cardiac cycles needed.
 
 Features (16 per site, host-side, from the generator's segment list), in
-one of two sets that differ in slots 1, 2 and 7-9:
+one of three sets that differ in slots 1, 2, 4-10:
   0  (r(t) - |x - q|) / r(t): wall distance relative to the local radius
   1  absolute: r(t) / 24, the local radius;
      scale_free: r(t) / r_ref, the radius relative to the parent segment's
@@ -29,6 +29,12 @@ one of two sets that differ in slots 1, 2 and 7-9:
   12 log10(k) + 2: wall stiffness of the segment
   13 u0 / 0.02: inlet amplitude
   14, 15 sin and cos of 2 pi (phase of the predicted state in the cycle)
+The local set keeps every input local and dimensionless: slot 1 as in the
+scale-free set, 2 the local Womersley number r sqrt(omega / nu) / 3, 4 and
+6 the distances to the segment's start and end in local radii (/ 16,
+capped at 1), 5 zero, 7 and 8 whether the segment starts and ends at a
+junction, 9 zero, 10 the prior's axial velocity in units of the section's
+mean-flow velocity; its outputs are corrections in that velocity too.
 Outputs (4): (rho - 1) / (10 u0), and the velocity / u0 in the segment's
 frame (axial, radial, azimuthal), each as a correction to a physics prior
 (`network_prior`): a linear one-dimensional model of the segment tree with
@@ -43,7 +49,9 @@ outside that range at every site, so the trees start from the prior; the
 scale-free set puts about 70 % of their sites inside it (the generation
 gate keeps generations 2 and deeper out), and the correction learned on
 single bifurcations then makes the trees' starts worse than the prior.
-The absolute set is the default.
+The local set puts half of the tree sites inside the range (the root and
+first-generation vessels are wider than any training tube) and does not
+help the trees either.  The absolute set is the default.
 """
 from __future__ import annotations
 
@@ -71,6 +79,7 @@ class SiteFrame:
     axis: np.ndarray     # [n, 3]
     radial: np.ndarray   # [n, 3]
     azim: np.ndarray     # [n, 3]
+    kind: str = "absolute"   # the feature set the static part belongs to
 
 
 def _topology(segs):
@@ -106,7 +115,7 @@ def _path_lengths(segs):
     return start, lengths, total, rem
 
 
-FEATURE_SETS = ("absolute", "scale_free")
+FEATURE_SETS = ("absolute", "scale_free", "local")
 
 
 def site_frames(geo: inputs.Geometry, feature_set: str = "absolute") -> SiteFrame:
@@ -118,10 +127,14 @@ def site_frames(geo: inputs.Geometry, feature_set: str = "absolute") -> SiteFram
     pos = np.stack([xx, yy, zz], 1).astype(np.float64)
     n_id = max(s.sid for s in segs) + 1
     # per-segment constants, gathered per site (segments are few)
-    parent, _ = _topology(segs)
+    parent, children = _topology(segs)
     RREF = np.ones(n_id)
+    UPJ = np.zeros(n_id)
+    DNJ = np.zeros(n_id)
     for j, sg in enumerate(segs):
         RREF[sg.sid] = segs[parent[j]].r1 if parent[j] >= 0 else sg.r0
+        UPJ[sg.sid] = parent[j] >= 0
+        DNJ[sg.sid] = len(children[j]) > 0
     P0 = np.zeros((n_id, 3))
     A = np.zeros((n_id, 3))
     Ls = np.ones(n_id)
@@ -172,6 +185,11 @@ def site_frames(geo: inputs.Geometry, feature_set: str = "absolute") -> SiteFram
     if feature_set == "scale_free":
         static[:, 1] = r / RREF[sid]
         static[:, 2] = gen
+    elif feature_set == "local":
+        # slot 2 (the local Womersley number) is set with the drive
+        static[:, 1] = r / RREF[sid]
+        static[:, 7] = UPJ[sid]
+        static[:, 8] = DNJ[sid]
     else:
         static[:, 1] = r / 24.0
         static[:, 2] = r / r_in
@@ -179,9 +197,14 @@ def site_frames(geo: inputs.Geometry, feature_set: str = "absolute") -> SiteFram
         static[:, 8] = gen == 1
         static[:, 9] = gen >= 2
     static[:, 3] = t
-    static[:, 4] = path
-    static[:, 6] = (lengths * (1.0 - t) + rem) / r_in / 40.0
-    return SiteFrame(static, r, sid, a, radial, azim)
+    if feature_set == "local":
+        # distances to the segment's start and end in local radii
+        static[:, 4] = np.minimum(t * lengths / r, 16.0) / 16.0
+        static[:, 6] = np.minimum((1.0 - t) * lengths / r, 16.0) / 16.0
+    else:
+        static[:, 4] = path
+        static[:, 6] = (lengths * (1.0 - t) + rem) / r_in / 40.0
+    return SiteFrame(static, r, sid, a, radial, azim, feature_set)
 
 
 def features(frame: SiteFrame, k_seg: Sequence[float], u0: float, phase: float,
@@ -191,8 +214,13 @@ def features(frame: SiteFrame, k_seg: Sequence[float], u0: float, phase: float,
     n = frame.static.shape[0]
     X = np.empty((n, N_FEAT), np.float32)
     X[:, :12] = frame.static
-    X[:, 5] = prior.Y[:, 0]
-    X[:, 10] = prior.Y[:, 1]
+    if frame.kind == "local":
+        X[:, 2] = frame.r * prior.kappa / 3.0          # local Womersley number / 3
+        X[:, 5] = 0.0
+        X[:, 10] = prior.Y[:, 1] / prior.scale         # in the local flow velocity
+    else:
+        X[:, 5] = prior.Y[:, 0]
+        X[:, 10] = prior.Y[:, 1]
     X[:, 11] = prior.slip
     X[:, 12] = np.log10(np.asarray(k_seg, np.float64)[frame.seg]) + 2.0
     X[:, 13] = u0 / 0.02
@@ -232,6 +260,8 @@ def _womersley(r, s, kw):
 class Prior:
     Y: np.ndarray        # [n, 4] estimate in output units
     slip: np.ndarray     # [n] slip factor at the mean pressure
+    scale: Optional[np.ndarray] = None   # [n] mean-flow velocity of the section / u0
+    kappa: float = 0.0   # sqrt(omega / nu): r kappa is the local Womersley number
 
 
 def network_prior(geo: inputs.Geometry, frame: SiteFrame, k_seg, F: float, P0: float, u0: float,
@@ -379,7 +409,8 @@ def network_prior(geo: inputs.Geometry, frame: SiteFrame, k_seg, F: float, P0: f
     P = np.zeros((len(seg), N_OUT), np.float32)
     P[:, 0] = (3.0 * p - 1.0) / (10.0 * u0)
     P[:, 1] = u_ax / u0
-    return Prior(P, sl.astype(np.float32))
+    scale = np.maximum(Q[g] / area / u0, 0.05).astype(np.float32)
+    return Prior(P, sl.astype(np.float32), scale, math.sqrt(omega / nu))
 
 
 def targets(frame: SiteFrame, rho, u, u0) -> np.ndarray:
@@ -462,7 +493,7 @@ def collect_batch(wl: workloads.Workload, dtype="f16", phases=8, sites_per_phase
         n = fr.static.shape[0]
         idx = np.sort(rng.choice(n, min(sites_per_phase, n), replace=False))
         subs.append((idx, SiteFrame(fr.static[idx], fr.r[idx], fr.seg[idx], fr.axis[idx],
-                                    fr.radial[idx], fr.azim[idx])))
+                                    fr.radial[idx], fr.azim[idx], fr.kind)))
     Xs, Ts = [], []
     step = period // phases
     for ph in range(phases):
@@ -478,7 +509,7 @@ def collect_batch(wl: workloads.Workload, dtype="f16", phases=8, sites_per_phase
             pr = network_prior(wl.geoms[k], sub, p.k, p.F, p.P0, u0, phase, nu=nu,
                                amp=p.iolets[0]["amp"], period=period)
             Xs.append(features(sub, p.k, u0, phase, pr))
-            Ts.append(targets(sub, rho[idx], u[idx], u0) - pr.Y)
+            Ts.append((targets(sub, rho[idx], u[idx], u0) - pr.Y) / out_scale(sub, pr)[:, None])
         lat.step(step)
     lat.close()
     return np.concatenate(Xs), np.concatenate(Ts), res
@@ -488,15 +519,25 @@ GEN_SLOTS = range(7, 10)
 TRUST = 1.0
 
 
+def out_scale(frame: SiteFrame, prior: Prior) -> np.ndarray:
+    """Unit of the network's correction per site, in output units: 1 (u0,
+    and 10 u0 for the density), or for the local feature set the prior's
+    mean-flow velocity of the site's section."""
+    if frame.kind == "local":
+        return prior.scale.astype(np.float32)
+    return np.ones(frame.static.shape[0], np.float32)
+
+
 def new_net(seed=0, width=128, depth=4, feature_set="absolute"):
     """Network with the standard shape for the given feature set; the
-    first-layer weights of the generation one-hot inputs start at zero, so
-    generations absent from the training data contribute nothing at
-    inference."""
+    first-layer weights of the generation one-hot inputs (absolute set)
+    start at zero, so generations absent from the training data contribute
+    nothing at inference."""
     from . import mlp
     p = mlp.init_params(N_FEAT, width, depth, N_OUT, seed=seed)
     W0 = p[:N_FEAT * width].reshape(width, N_FEAT)
-    W0[:, list(GEN_SLOTS)] = 0.0
+    if feature_set == "absolute":
+        W0[:, list(GEN_SLOTS)] = 0.0
     net = mlp.Net(N_FEAT, width, depth, N_OUT, params=p)
     net.feature_set = feature_set
     return net
@@ -578,13 +619,14 @@ def predict(net, geo, frame: SiteFrame, params, phase, nu=0.1, chunk=1 << 20, us
             ok = np.ones(X.shape[0], bool)
         else:
             ok = in_range(X, fr)
+        unit = out_scale(frame, pr)
         for s in range(0, X.shape[0], chunk):
             xb = net.to_bf16(torch.tensor(X[s:s + chunk], device="cuda"))
             # trust region: the correction to the prior is at most one output
             # unit (u0 in velocity, 10 u0 in density), and none at sites
             # whose features lie outside the training range
             dY = np.clip(net.infer_fused(xb).cpu().numpy(), -TRUST, TRUST)
-            Y[s:s + chunk] += dY * ok[s:s + chunk, None]
+            Y[s:s + chunk] += dY * (ok[s:s + chunk] * unit[s:s + chunk])[:, None]
     return assemble(frame, Y, u0)
 
 

@@ -139,6 +139,32 @@ def test_feature_layout():
     assert np.allclose(X[:, 14], math.sin(0.2 * math.pi)) and np.allclose(X[:, 15], math.cos(0.2 * math.pi))
 
 
+def test_local_feature_layout():
+    """The local set on one tube of radius 8 (no junctions): radius over the
+    reference 1, the local Womersley number r sqrt(omega / nu) / 3,
+    distances to the ends in radii (/ 16, capped), junction flags 0, the
+    prior's axial velocity in the section's mean-flow velocity, and the
+    correction unit of each site that velocity (here u0: one section)."""
+    g, _ = _tube()
+    fr = warmstart.site_frames(g, "local")
+    assert fr.kind == "local"
+    P = warmstart.network_prior(g, fr, [0.01], 0.5, 1 / 3, 0.02, 0.1, nu=NU)
+    X = warmstart.features(fr, [0.01], 0.02, 0.1, P)
+    kappa = math.sqrt(2 * math.pi / 4000.0 / NU)
+    assert np.allclose(P.kappa, kappa)
+    assert np.all(X[:, 1] == 1.0) and np.allclose(X[:, 2], 8.0 * kappa / 3.0)
+    L = float(np.linalg.norm(g.segments[0].p1 - g.segments[0].p0))
+    t = fr.static[:, 3].astype(np.float64)
+    assert np.allclose(X[:, 4], np.minimum(t * L / 8.0, 16.0) / 16.0, atol=1e-6)
+    assert np.allclose(X[:, 6], np.minimum((1 - t) * L / 8.0, 16.0) / 16.0, atol=1e-6)
+    assert np.all(X[:, 5] == 0.0) and np.all(X[:, 7:10] == 0.0)
+    assert np.allclose(P.scale, 1.0)
+    assert np.allclose(X[:, 10], P.Y[:, 1] / P.scale)
+    assert np.array_equal(warmstart.out_scale(fr, P), P.scale)
+    absolute = warmstart.site_frames(g)
+    assert np.all(warmstart.out_scale(absolute, P) == 1.0)
+
+
 def test_tree_features_are_free_of_the_scale():
     """With the scale-free feature set, on a Murray tree the radius feature
     is r(t) over the parent's end radius and the generation feature is the
