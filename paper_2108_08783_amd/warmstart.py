@@ -750,9 +750,12 @@ def summarize(results):
 def experiment(train_batches=4, train_per_batch=64, train_sites=20e6, test_sweep=16,
                test_sweep_sites=5e6, test_trees=16, tree_first=0, tree_scale=1.0, dtype="f32",
                epochs=30, sites_per_phase=2048, max_cycles=12, seed=0, net_params=None,
-               save_net=None, checkpoint=None, log=print, feature_set="absolute"):
+               save_net=None, checkpoint=None, log=print, feature_set="absolute",
+               train_trees=0):
     """Train on cold-started sweep batches (seeds 1000.., run to
-    periodicity, sampled at 8 phases) unless `net_params` is given, then
+    periodicity, sampled at 8 phases), or with `train_trees` > 0 on batches
+    of that many Murray trees (seeds 1000.., disjoint from the held-out
+    trees' 2000..), unless `net_params` is given, then
     start held-out sweep instances (seed 3000) and Murray trees (seeds
     2000 + tree_first ..) cold, from the prior and from the network, and
     run each to periodicity.  The trained parameters are written to
@@ -760,17 +763,22 @@ def experiment(train_batches=4, train_per_batch=64, train_sites=20e6, test_sweep
     called with the results so far after each evaluated workload.  Returns
     (JSON-ready dict, network)."""
     t_all = time.perf_counter()
-    out = dict(config=dict(train_instances=train_batches * train_per_batch,
+    out = dict(config=dict(train_instances=train_batches * (train_trees or train_per_batch),
                            train_sites_per_batch=train_sites, test_sweep=test_sweep,
                            test_sweep_sites=test_sweep_sites, test_trees=test_trees,
                            tree_first=tree_first, tree_scale=tree_scale, dtype=dtype,
                            epochs=epochs, sites_per_phase=sites_per_phase, tol=1e-3,
-                           period=int(workloads.PERIOD), feature_set=feature_set))
+                           period=int(workloads.PERIOD), feature_set=feature_set,
+                           train_trees=train_trees))
     if net_params is None:
         Xs, Ts, train_cycles = [], [], []
         t0 = time.perf_counter()
         for b in range(train_batches):
-            wl = workloads.sweep(seed=1000 + b, n=train_per_batch, target_sites=train_sites)
+            if train_trees:
+                wl = workloads.trees([1000 + b * train_trees + j for j in range(train_trees)],
+                                     scale=tree_scale)
+            else:
+                wl = workloads.sweep(seed=1000 + b, n=train_per_batch, target_sites=train_sites)
             X, T, res = collect_batch(wl, dtype, sites_per_phase=sites_per_phase,
                                       max_cycles=max_cycles, seed=b, feature_set=feature_set)
             Xs.append(X)
@@ -835,6 +843,11 @@ def main(argv=None):
     ap.add_argument("--tree-first", type=int, default=0)
     ap.add_argument("--tree-scale", type=float, default=1.0)
     ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--train-trees", type=int, default=0,
+                    help="train on batches of this many Murray trees (seeds 1000..) "
+                         "instead of sweep batches")
+    ap.add_argument("--sites-per-phase", type=int, default=2048,
+                    help="training sites sampled per instance and phase")
     ap.add_argument("--dtype", default="f32")
     ap.add_argument("--save-net", default=None,
                     help="write the trained parameters and feature range (.npz)")
@@ -868,9 +881,10 @@ def main(argv=None):
                     f.write(json.dumps(d) + "\n")
         r, net = experiment(a.train_batches, a.train_per_batch, a.train_sites, a.test_sweep,
                             a.test_sweep_sites, a.test_trees, a.tree_first, a.tree_scale,
-                            a.dtype, a.epochs, net_params=p, save_net=a.save_net,
+                            a.dtype, a.epochs, sites_per_phase=a.sites_per_phase,
+                            net_params=p, save_net=a.save_net,
                             checkpoint=save, log=lambda m: print(m, flush=True),
-                            feature_set=a.features)
+                            feature_set=a.features, train_trees=a.train_trees)
     if a.out:
         with open(a.out, "w") as f:
             f.write(json.dumps(r) + "\n")

@@ -75,6 +75,14 @@ def tree(seed=3, scale=1.0, period=PERIOD):
                     info=dict(seed=seed, scale=scale))
 
 
+def trees(seeds, scale=1.0, period=PERIOD):
+    """Several Murray trees (as `tree`) as the instances of one workload."""
+    wls = [tree(sd, scale, period) for sd in seeds]
+    return Workload(f"{len(wls)} murray trees seeds {list(seeds)} scale {scale}",
+                    [w.geoms[0] for w in wls], [w.params[0] for w in wls],
+                    info=dict(seeds=list(seeds), scale=scale))
+
+
 def sweep(seed=4, n=64, target_sites=20e6, period=PERIOD):
     geos, prm = inputs.batch(seed, n=n, target_sites=target_sites)
     params = [InstanceParams(lbm.ELASTIC, 0.5, 1.0 / 3.0, [q["k"]] * g.n_seg,
