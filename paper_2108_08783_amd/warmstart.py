@@ -687,6 +687,11 @@ MODES = ("cold", "prior", "warm")
 # 30 epochs): python -m paper_2108_08783_amd.warmstart --test-sweep 16
 # --test-trees 4 --save-net <file>, parameters stored as float32.
 NET_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "warmstart_net.npz")
+# the same network shape trained on 32 Murray trees (seeds 1000-1031; absolute
+# features, 4.2M samples): for tree-shaped vessels, outside the protocol of
+# NET_FILE's tubes and single bifurcations
+TREE_NET_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data",
+                             "warmstart_net_trees.npz")
 
 
 def save_net_file(path, net):

@@ -64,3 +64,26 @@ def test_trained_network_beats_the_prior_on_held_out_instances():
     assert sum(cyc["warm"]) <= sum(cyc["prior"]) <= sum(cyc["cold"])
     assert any(w < p for w, p in zip(cyc["warm"], cyc["prior"]))
     assert du["warm"].sum() < 0.7 * du["prior"].sum()
+
+
+def test_tree_trained_network_beats_the_prior_on_held_out_trees():
+    """The committed network trained on 32 Murray trees (seeds 1000-1031)
+    on the first four held-out trees (seeds 2000-2003, 7.2-7.7M sites
+    each): every start reaches the cold periodic state (2e-3), the network
+    start needs no more cycles than the prior on any tree and fewer in
+    total."""
+    from paper_2108_08783_amd import warmstart, workloads
+    net = warmstart.load_net(dict(np.load(warmstart.TREE_NET_FILE)))
+    assert net.feature_set == "absolute"
+    cyc = {m: [] for m in warmstart.MODES}
+    for seed in range(2000, 2004):
+        cmp = warmstart.compare_starts(net, workloads.tree(seed=seed), "f32", max_cycles=12,
+                                       log=print)
+        for m in warmstart.MODES:
+            cyc[m] += cmp[m].cycles
+        print({"seed": seed, **{m: cmp[m].cycles for m in warmstart.MODES},
+               "state_diff": max(cmp["state_diff"])}, flush=True)
+        assert max(cmp["state_diff"]) <= 2e-3
+    assert all(c > 0 for m in cyc for c in cyc[m])
+    assert all(w <= p for w, p in zip(cyc["warm"], cyc["prior"]))
+    assert sum(cyc["warm"]) < sum(cyc["prior"]) <= sum(cyc["cold"])
