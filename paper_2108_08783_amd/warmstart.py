@@ -51,7 +51,9 @@ gate keeps generations 2 and deeper out), and the correction learned on
 single bifurcations then makes the trees' starts worse than the prior.
 The local set puts half of the tree sites inside the range (the root and
 first-generation vessels are wider than any training tube) and does not
-help the trees either.  The absolute set is the default.
+help the trees either.  The absolute set is the default.  Trained on
+branching trees instead (`train_trees`), the same network with the
+absolute set does help held-out trees; that network is TREE_NET_FILE.
 """
 from __future__ import annotations
 
