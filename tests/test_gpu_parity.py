@@ -552,9 +552,10 @@ _POP_BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
 def test_population_buffers_beyond_2GiB(dtype, launch):
     """Three random boxes (every link type; elastic and bounce-back walls)
     packed after a 16-63M-site cylinder, so that their upper population
-    planes lie beyond 2 GiB and the update uses 64-bit offsets: 60 steps,
-    each box against the oracle over every site with the random-box bounds;
-    the cylinder's fields must stay finite."""
+    planes lie beyond 2 GiB and the update uses 64-bit offsets (FP32 also
+    with table offsets and with two sites per lane, whose offsets then
+    count elements): 60 steps, each box against the oracle over every site
+    with the random-box bounds; the cylinder's fields must stay finite."""
     g = inputs.cylinder(48, _FILLER_L[dtype])
     filler = H.Problem(geo=g, tau=0.7, mode=lbm.ELASTIC, F=0.6, P0=0.999 / 3.0, k=[1e-2],
                        iolets={0: dict(kind=lbm.DENSITY, a0=1.001),
