@@ -56,3 +56,19 @@ def test_bifurcation_has_two_outlets():
     g = inputs.bifurcation(8, 120, 50)
     present = sorted({int(v) - 2 for v in np.unique(g.labels) if v >= 2})
     assert present == [0, 1, 2]
+
+
+def test_tree_batch_workload_holds_each_seeded_tree():
+    """`workloads.trees`: one instance per seed, each the tree (geometry and
+    parameters) that `workloads.tree` gives for that seed; the training
+    seeds of the tree-trained warm start (1000..) are disjoint from the
+    held-out ones (2000..)."""
+    from paper_2108_08783_amd import workloads
+    wl = workloads.trees([1000, 1001], scale=0.2)
+    assert len(wl.geoms) == len(wl.params) == 2
+    for k, seed in enumerate((1000, 1001)):
+        one = workloads.tree(seed, scale=0.2)
+        assert np.array_equal(wl.geoms[k].labels, one.geoms[0].labels)
+        assert wl.params[k].k == one.params[0].k and wl.params[k].F == one.params[0].F
+        assert wl.params[k].iolets.keys() == one.params[0].iolets.keys()
+    assert wl.n_sites == sum(g.n_fluid for g in wl.geoms)
